@@ -1,0 +1,322 @@
+"""Python handle on the FP64 CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product path (the HIP library
+and its binding) never imports this package.
+
+Each wrapper names the part of arXiv 2405.00698 it follows; the C source
+carries the details.
+"""
+import ctypes as C
+import math
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+GENOME_LEN = 8710
+NO_GRAVITY, NO_GROUND, NO_ACTUATION = 1, 2, 4
+
+
+def build(force=False):
+    """Compile liboracle.so with gcc (plain -O2, no fast-math, OpenMP over robots)."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
+                           SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+class _Params(C.Structure):
+    _fields_ = [("dt", C.c_double), ("gravity", C.c_double), ("damping", C.c_double),
+                ("mass", C.c_double), ("voxel_len", C.c_double), ("k_ground", C.c_double),
+                ("mu", C.c_double), ("act_freq", C.c_double),
+                ("k_class", C.c_double * 5), ("a_class", C.c_double * 5),
+                ("phi_class", C.c_double * 5), ("flags", C.c_int32)]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _up(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint8))
+
+
+def _u64p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_uint64))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        vp = C.c_void_p
+        L.or_robot_create.restype = vp
+        L.or_robot_create.argtypes = [C.POINTER(_Params), C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_double)]
+        L.or_robot_destroy.argtypes = [vp]
+        L.or_robot_counts.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.or_robot_voxels.argtypes = [vp, C.POINTER(C.c_uint8)]
+        L.or_robot_nodes.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.or_robot_springs.argtypes = [vp, C.POINTER(C.c_int32)] + [C.POINTER(C.c_double)] * 4
+        L.or_robot_set_springs.argtypes = [vp] + [C.POINTER(C.c_double)] * 3
+        L.or_robot_get_state.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+        L.or_robot_set_state.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int64]
+        L.or_robot_get_x0.argtypes = [vp, C.POINTER(C.c_double)]
+        L.or_robot_step.argtypes = [vp, C.c_int]
+        L.or_pop_step.argtypes = [C.POINTER(vp), C.c_int, C.c_int]
+        L.or_robot_fitness.restype = C.c_double
+        L.or_robot_fitness.argtypes = [vp]
+        L.or_robot_momentum.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_robot_energy.restype = C.c_double
+        L.or_robot_energy.argtypes = [vp]
+        L.or_robot_backward.restype = C.c_double
+        L.or_robot_backward.argtypes = [vp, C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 3
+        L.or_robot_dJdw.argtypes = [vp] + [C.POINTER(C.c_double)] * 3
+        L.or_mlp_backward.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_encode.argtypes = [C.POINTER(C.c_double)] * 3
+        L.or_mlp.argtypes = [C.POINTER(C.c_double)] * 5
+        L.or_query.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]
+        L.or_heads.argtypes = [C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_double)]
+        L.or_lcc.argtypes = [C.POINTER(C.c_uint8), C.c_int, C.POINTER(C.c_uint8)]
+        L.or_philox4x64_10.argtypes = [C.POINTER(C.c_uint64)] * 3
+        L.or_ga_generation.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.c_int, C.c_int, C.c_double, C.c_int, C.c_uint64, C.c_uint64,
+                                       C.c_double, C.c_uint64, C.c_uint64, C.POINTER(C.c_int32)]
+        L.or_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+# Default parameters: the hot-path configuration (voxel edge 0.1 m, 0.1 kg per
+# node and ground stiffness 1e5 N/m as in Table II; dt, damping, friction,
+# stiffness per class and the 4 Hz, +-0.2 muscle law from the workload spec).
+DEFAULTS = dict(dt=1e-4, gravity=9.81, damping=0.999, mass=0.1, voxel_len=0.1,
+                k_ground=1e5, mu=0.5, act_freq=4.0,
+                k_class=(0.0, 1e4, 1e4, 3e3, 3e4), a_class=(0.0, 0.2, -0.2, 0.0, 0.0),
+                phi_class=(0.0,) * 5, flags=0)
+
+
+def make_params(**kw):
+    d = dict(DEFAULTS)
+    d.update(kw)
+    p = _Params()
+    for k in ("dt", "gravity", "damping", "mass", "voxel_len", "k_ground", "mu", "act_freq"):
+        setattr(p, k, float(d[k]))
+    p.k_class = (C.c_double * 5)(*d["k_class"])
+    p.a_class = (C.c_double * 5)(*d["a_class"])
+    p.phi_class = (C.c_double * 5)(*d["phi_class"])
+    p.flags = int(d["flags"])
+    return p
+
+
+class Robot:
+    """One voxel robot in the oracle (Sec. II-A; build, step, fitness, adjoint)."""
+
+    def __init__(self, n, cls, w, **params):
+        self.n = int(n)
+        self.params = dict(DEFAULTS, **params)
+        cls = np.ascontiguousarray(cls, dtype=np.uint8).reshape(-1)
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        assert cls.size == n ** 3 and w.size == n ** 3
+        self._p = make_params(**params)
+        self.h = lib().or_robot_create(C.byref(self._p), self.n, _up(cls), _dp(w))
+        if not self.h:
+            raise ValueError("robot has no occupied voxel")
+        M, S = C.c_int32(), C.c_int32()
+        lib().or_robot_counts(self.h, C.byref(M), C.byref(S))
+        self.M, self.S = M.value, S.value
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.or_robot_destroy(h)
+            self.h = None
+
+    def kept(self):
+        out = np.zeros(self.n ** 3, np.uint8)
+        lib().or_robot_voxels(self.h, _up(out))
+        return out
+
+    def node_lattice(self):
+        out = np.zeros(self.M, np.int32)
+        lib().or_robot_nodes(self.h, _ip(out))
+        return out
+
+    def springs(self):
+        ij = np.zeros((self.S, 2), np.int32)
+        L0, k, a, phi = (np.zeros(self.S) for _ in range(4))
+        lib().or_robot_springs(self.h, _ip(ij), _dp(L0), _dp(k), _dp(a), _dp(phi))
+        return dict(ij=ij, L0=L0, k=k, a=a, phi=phi)
+
+    def set_springs(self, k=None, a=None, phi=None):
+        arr = [None if t is None else np.ascontiguousarray(t, dtype=np.float64) for t in (k, a, phi)]
+        lib().or_robot_set_springs(self.h, *[_dp(t) if t is not None else None for t in arr])
+
+    def state(self):
+        x = np.zeros((self.M, 3))
+        v = np.zeros((self.M, 3))
+        st, dv = C.c_int64(), C.c_int32()
+        lib().or_robot_get_state(self.h, _dp(x), _dp(v), C.byref(st), C.byref(dv))
+        return x, v, st.value, bool(dv.value)
+
+    def set_state(self, x, v, step):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        lib().or_robot_set_state(self.h, _dp(x), _dp(v), int(step))
+
+    def x0(self):
+        x = np.zeros((self.M, 3))
+        lib().or_robot_get_x0(self.h, _dp(x))
+        return x
+
+    def step(self, n_steps):
+        lib().or_robot_step(self.h, int(n_steps))
+
+    def fitness(self):
+        return lib().or_robot_fitness(self.h)
+
+    def momentum(self):
+        P = np.zeros(3)
+        Lm = np.zeros(3)
+        lib().or_robot_momentum(self.h, _dp(P), _dp(Lm))
+        return P, Lm
+
+    def energy(self):
+        return lib().or_robot_energy(self.h)
+
+    def backward(self, n_steps, g=1.0):
+        """J = g * fitness after n_steps from the current state, and dJ/d(k, a, phi) per spring."""
+        gk, ga, gp = (np.zeros(self.S) for _ in range(3))
+        J = lib().or_robot_backward(self.h, int(n_steps), float(g), _dp(gk), _dp(ga), _dp(gp))
+        return J, gk, ga, gp
+
+    def dJdw(self, gk, ga):
+        out = np.zeros(self.n ** 3)
+        rc = lib().or_robot_dJdw(self.h, _dp(np.ascontiguousarray(gk, dtype=np.float64)),
+                                 _dp(np.ascontiguousarray(ga, dtype=np.float64)), _dp(out))
+        if rc != 0:
+            raise ValueError("genome gradient needs all class phases zero")
+        return out
+
+
+def pop_step(robots, n_steps):
+    """Step many robots, one per host thread."""
+    arr = (C.c_void_p * len(robots))(*[r.h for r in robots])
+    lib().or_pop_step(arr, len(robots), int(n_steps))
+
+
+def num_threads():
+    return lib().or_num_threads()
+
+
+def encode(B, v):
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    g = np.zeros(64)
+    lib().or_encode(_dp(B), _dp(v), _dp(g))
+    return g
+
+
+def mlp(genome, g):
+    genome = np.ascontiguousarray(genome, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    h1, h2, o = np.zeros(64), np.zeros(64), np.zeros(6)
+    lib().or_mlp(_dp(genome), _dp(g), _dp(h1), _dp(h2), _dp(o))
+    return h1, h2, o
+
+
+def query(genome, B, n):
+    """Logits [n^3, 6] of one genome over an n^3 grid (Eq. (1) + MLP)."""
+    genome = np.ascontiguousarray(genome, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    out = np.zeros((n ** 3, 6))
+    lib().or_query(_dp(genome), _dp(B), int(n), _dp(out))
+    return out
+
+
+def heads(logits):
+    logits = np.ascontiguousarray(logits, dtype=np.float64)
+    nv = logits.shape[0]
+    cls = np.zeros(nv, np.uint8)
+    w = np.zeros(nv)
+    lib().or_heads(_dp(logits), nv, _up(cls), _dp(w))
+    return cls, w
+
+
+def lcc(cls, n):
+    cls = np.ascontiguousarray(cls, dtype=np.uint8).reshape(-1)
+    kept = np.zeros(n ** 3, np.uint8)
+    lib().or_lcc(_up(cls), int(n), _up(kept))
+    return kept
+
+
+def mlp_backward(genome, B, n, dJdw):
+    genome = np.ascontiguousarray(genome, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    dJdw = np.ascontiguousarray(dJdw, dtype=np.float64)
+    out = np.zeros(GENOME_LEN)
+    lib().or_mlp_backward(_dp(genome), _dp(B), int(n), _dp(dJdw), _dp(out))
+    return out
+
+
+def philox(ctr, key):
+    c = np.array(ctr, dtype=np.uint64)
+    k = np.array(key, dtype=np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().or_philox4x64_10(_u64p(c), _u64p(k), _u64p(out))
+    return out
+
+
+def prob_threshold(p):
+    """floor(p * 2^64) as an unsigned 64-bit threshold (p in [0, 1])."""
+    if p >= 1.0:
+        return 2 ** 64 - 1
+    return int(math.floor(p * 2.0 ** 64))
+
+
+def ga_generation(fitness, genomes, elite_frac=0.3, k=4, p_cross=0.4, p_mut=0.1, sigma=0.02,
+                  seed=3, generation=0, p_cross_thr=None, p_mut_thr=None):
+    """One GA generation (Sec. II-C, Table I).  Returns (children, decisions[P,3])."""
+    fit = np.ascontiguousarray(fitness, dtype=np.float64)
+    gin = np.ascontiguousarray(genomes, dtype=np.float64)
+    P, L = gin.shape
+    gout = np.zeros_like(gin)
+    dec = np.zeros((P, 3), np.int32)
+    ct = prob_threshold(p_cross) if p_cross_thr is None else p_cross_thr
+    mt = prob_threshold(p_mut) if p_mut_thr is None else p_mut_thr
+    rc = lib().or_ga_generation(_dp(fit), _dp(gin), _dp(gout), P, L, float(elite_frac), int(k),
+                                ct, mt, float(sigma), int(seed), int(generation), _ip(dec))
+    assert rc == 0
+    return gout, dec
+
+
+def robot_from_genome(genome, B, n, **params):
+    """Full build (Eq. (1) -> MLP -> heads -> robot)."""
+    lg = query(genome, B, n)
+    cls, w = heads(lg)
+    return Robot(n, cls, w, **params)
+
+
+def genome_fitness_grad(genome, B, n, n_steps, **params):
+    """J = fitness after n_steps of the robot built from `genome`, and dJ/dgenome."""
+    R = robot_from_genome(genome, B, n, **params)
+    J, gk, ga, gp = R.backward(n_steps)
+    dJdw = R.dJdw(gk, ga)
+    return J, mlp_backward(genome, B, n, dJdw)
