@@ -1,0 +1,163 @@
+#!/usr/bin/env python3
+"""Benchmark of the soft-robot co-design hot path on one MI355X.
+
+One bench step is one generation of the co-design loop over the throughput
+workload (4096 robots on 10x10x10 grids, random genomes): genome query and
+mesh build, 10,000 simulation steps in the persistent LDS-resident kernel,
+fitness, and the GA generation that produces the next genomes.  The metric is
+spring updates per second over the whole generation.
+
+Prints one JSON line (rank 0).  Only one GPU is supported: the population
+would shard across GPUs by robots, which this benchmark does not run.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# roofline denominators (MI355X: 256 CUs at 2.4 GHz)
+CU, CLK = 256, 2.4e9
+LDS_PEAK_GBS = CU * 128 * CLK / 1e9          # 128 B/clk/CU LDS bandwidth
+VALU_PEAK_SLOTS = CU * 64 * CLK               # FP32 lane-op issue slots/s without packed math
+LDS_B_PER_SPRING = 24.0                      # both endpoint positions, FP32 xyz
+LDS_B_PER_MASS = 12.0                        # each mass publishes its position
+VALU_SLOTS_PER_SPRING = 18.0                 # one force evaluation applied to both ends
+VALU_SLOTS_PER_MASS = 20.0                   # gravity, ground, friction, damping, integrate
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--robots", type=int, default=4096)
+    ap.add_argument("--side", type=int, default=10)
+    ap.add_argument("--sim-steps", type=int, default=10000)
+    ap.add_argument("--mode", default="persistent", choices=["persistent", "plain"])
+    ap.add_argument("--query", default="fp32", choices=["bf16", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=5000)
+    ap.add_argument("--cpu-robots", type=int, default=64)
+    return ap.parse_args()
+
+
+def cpu_baseline(args, genomes, B):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    import oracle
+    from paper_2405_00698_amd import inputs  # noqa: F401
+    oracle.build()
+    robots = [oracle.robot_from_genome(genomes[r].astype(np.float64), B.astype(np.float64), args.side)
+              for r in range(args.cpu_robots)]
+    S = sum(R.S for R in robots)
+    t = time.perf_counter()
+    oracle.pop_step(robots, args.cpu_steps)
+    dt = time.perf_counter() - t
+    return {"value": S * args.cpu_steps / dt, "unit": "spring updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "%d robots of %d^3 from the same genomes, %d steps, FP64, one robot per thread (%.1f s)"
+                      % (args.cpu_robots, args.side, args.cpu_steps, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only; the population shards by robots across GPUs, "
+              "which this build does not launch (got --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2405_00698_amd import inputs, api, _lib
+    from paper_2405_00698_amd import SR_QUERY_BF16, SR_QUERY_FP32, SR_STEP_PLAIN, SR_STEP_AUTO
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    R, n = args.robots, args.side
+    B = inputs.gaussian_B()
+    G = inputs.random_genomes(R)
+    Bt = torch.from_numpy(B).to(dev)
+    Gt = [torch.from_numpy(G).to(dev), torch.empty((R, _lib.GENOME_LEN), dtype=torch.float32, device=dev)]
+    fit = torch.empty(R, dtype=torch.float32, device=dev)
+    P = api.Population([n] * R)
+    P.set_step_config(SR_STEP_PLAIN if args.mode == "plain" else SR_STEP_AUTO)
+    prec = SR_QUERY_BF16 if args.query == "bf16" else SR_QUERY_FP32
+    has_ga = hasattr(_lib.load(), "ga_generation")
+    if has_ga:
+        from paper_2405_00698_amd.api import ga_generation, GAConfig
+        gacfg = GAConfig()
+
+    stream = torch.cuda.current_stream()
+    springs_per_gen = []
+    sim_ms = []
+
+    def one_generation(g, record):
+        # without the GA the same genomes are rebuilt every generation
+        cur = Gt[g % 2] if has_ga else Gt[0]
+        P.build_from_genomes(cur, Bt, prec)
+        M, S, _, _ = P.counts()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        P.step(args.sim_steps)
+        e1.record(stream)
+        P.fitness(fit)
+        if has_ga:
+            ga_generation(fit, cur, Gt[(g + 1) % 2], gacfg, seed=inputs.SEED_GA, generation=g)
+        if record:
+            springs_per_gen.append((sum(S), sum(M)))
+            sim_ms.append((e0, e1))
+
+    for g in range(args.warmup):
+        one_generation(g, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(args.warmup, args.warmup + args.steps):
+        one_generation(g, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    total_springs = sum(s for s, _ in springs_per_gen) * args.sim_steps
+    total_masses = sum(m for _, m in springs_per_gen) * args.sim_steps
+    value = total_springs / wall
+    kern_s = sum(a.elapsed_time(b) for a, b in sim_ms) / 1e3 / len(sim_ms)
+    su_per_launch = total_springs / len(sim_ms)
+    mu_per_launch = total_masses / len(sim_ms)
+    lds_bytes = su_per_launch * LDS_B_PER_SPRING + mu_per_launch * LDS_B_PER_MASS
+    lds_gbs = lds_bytes / kern_s / 1e9
+    valu = (su_per_launch * VALU_SLOTS_PER_SPRING + mu_per_launch * VALU_SLOTS_PER_MASS) / kern_s
+    out = {
+        "metric": "spring updates/sec at 1 GPU (% LDS roofline); adjoint/forward time ratio",
+        "value": value,
+        "unit": "spring updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded random genomes (W ~ N(0, 1/64), b = 0), B ~ N(0, 1)",
+        "config": {"workload": "%d robots on %d^3 voxel grids, %d sim steps per generation (dt 1e-4 s), "
+                               "%s genome query, GA %s" % (R, n, args.sim_steps, args.query,
+                                                            "on" if has_ga else "off"),
+                   "robots": R, "grid_side": n, "sim_steps": args.sim_steps, "mode": args.mode,
+                   "springs_per_generation": springs_per_gen[0][0], "masses_per_generation": springs_per_gen[0][1]},
+        "sim_kernel_s": kern_s,
+        "sim_spring_updates_per_s": su_per_launch / kern_s,
+        "roofline": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": lds_gbs / LDS_PEAK_GBS, "traffic": None},
+        "roofline_alu": {"bound": "alu", "achieved": valu / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                         "unit": "T lane-op slots/s", "frac": valu / VALU_PEAK_SLOTS},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, G, B)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,124 @@
+// internal.h -- declarations shared by the library's own translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/softrobot.h"
+
+namespace sr {
+
+// Lattice stencil.  Every spring of a voxel robot joins two lattice points of
+// one voxel, so it points along one of 13 directions up to sign: 3 edges,
+// 6 face diagonals, 4 body diagonals.  They are listed in lexicographic
+// (dz, dy, dx) order, which is the order of the neighbour's lattice index, so a
+// node's forward springs come out in canonical (lower id, higher id) order.
+constexpr int NDIR = 13;
+__host__ __device__ constexpr int dir_dx(int d) {
+    return d == 0 ? 1 : d == 1 ? -1 : d == 2 ? 0 : d == 3 ? 1 : d == 4 ? -1 : d == 5 ? 0 : d == 6 ? 1
+         : d == 7 ? -1 : d == 8 ? 0 : d == 9 ? 1 : d == 10 ? -1 : d == 11 ? 0 : 1;
+}
+__host__ __device__ constexpr int dir_dy(int d) {
+    return d == 0 ? 0 : d == 1 ? 1 : d == 2 ? 1 : d == 3 ? 1 : d <= 6 ? -1 : d <= 9 ? 0 : 1;
+}
+__host__ __device__ constexpr int dir_dz(int d) { return d <= 3 ? 0 : 1; }
+// squared lattice length: 1 edge, 2 face diagonal, 3 body diagonal
+__host__ __device__ constexpr int dir_len2(int d) {
+    return dir_dx(d) * dir_dx(d) + dir_dy(d) * dir_dy(d) + dir_dz(d) * dir_dz(d);
+}
+// linear offset of direction d on a lattice of side N (index a + N (b + N c))
+__host__ __device__ constexpr int dir_off(int d, int N) { return dir_dx(d) + N * (dir_dy(d) + N * dir_dz(d)); }
+
+// Per-robot metadata, device resident.
+struct RobotInfo {
+    int32_t n;          // voxels per side
+    int32_t N;          // lattice points per side, n + 1
+    int32_t slots;      // N^3
+    int32_t slot_base;  // offset of the robot's lattice slots in slot-indexed arrays
+    int32_t vox_base;   // offset of its voxels in voxel arrays
+    int32_t M;          // nodes (written by the build)
+    int32_t S;          // springs (written by the build)
+    int32_t pad;
+};
+
+// Spring parameters live in four stencil planes, each [13][slots] per robot
+// (plane index 13 * slot_base + d * slots + lower_slot):
+//   k     stiffness (0 where no spring)
+//   kL0   k * L0
+//   kal   k * L0 * a cos(phi)   (coefficient of sin(w t) in k L(t))
+//   kbe   k * L0 * a sin(phi)   (coefficient of cos(w t))
+// so that k L(t) = kL0 + kal sin(w t) + kbe cos(w t).
+struct Planes {
+    float *k, *kL0, *kal, *kbe;
+};
+
+// Node incidence for the per-step kernel: for node i of a robot (slot-space
+// index slot_base + i), its global slot and the ranges of its forward
+// (lower endpoint) and backward (upper endpoint) entries.
+struct NodeRow {
+    int32_t gslot, start, mid, end;
+};
+struct Entry {
+    int32_t nbr;   // global slot of the other endpoint
+    int32_t plane; // global plane index of the spring
+};
+
+struct SimConst {
+    float dt, dt_m, damping, mg, kc, mu_kc_dt_m, lim;
+    float L0e, L0f, L0b;  // rest lengths of edge, face-diagonal, body-diagonal springs
+    int32_t gravity, ground, actuation;
+};
+
+SimConst make_sim_const(const sr_sim_params &p);
+
+// ---- kernels (launchers); each returns hipError_t of the launch ----
+hipError_t launch_build_mesh(const RobotInfo *robots, int R, int max_side, const sr_sim_params &p,
+                             const uint8_t *cls, const float *w, uint8_t *kept, Planes pl,
+                             int32_t *sid, float4 *x0, float4 *x, float4 *v, int32_t *slot_node,
+                             int32_t *node_slot, NodeRow *rows, Entry *entries, uint8_t *bad_class,
+                             uint8_t *diverged, hipStream_t st);
+
+hipError_t launch_query(const RobotInfo *robots, int R, int max_side, const float *genomes, const float *B,
+                        int precision, uint8_t *cls, float *w, hipStream_t st);
+
+hipError_t launch_ga(const float *fit, const float *gin, float *gout, int P, int L, int E, int k, uint64_t pc,
+                     uint64_t pm, float sigma, uint64_t seed, uint64_t gen, int32_t *dec, hipStream_t st);
+
+hipError_t launch_sincos(float2 *sc, const int64_t *d_step, int n, double omega_dt, int on, hipStream_t st);
+hipError_t launch_advance(int64_t *d_step, int n, hipStream_t st);
+
+hipError_t launch_plain_step(const RobotInfo *robots, int R, int total_slots, const NodeRow *rows,
+                             const Entry *entries, Planes pl, const float4 *x, const float4 *v,
+                             float4 *xn, float4 *vn, const float2 *sc, int t, bool phase,
+                             const uint8_t *diverged, const int32_t *slot_robot, SimConst c, hipStream_t st);
+
+hipError_t launch_check_div(const RobotInfo *robots, int R, const float4 *x, const float4 *v,
+                            uint8_t *diverged, float lim, hipStream_t st);
+
+// persistent LDS-resident kernel for robots of side n; `list` holds the robot
+// ids to step (all of side n).  variant: 0 recompute, 1 exchange, 2 exchange
+// in two direction chunks.
+struct PersistCfg {
+    int n, block, variant;
+};
+bool persist_supported(const PersistCfg &cfg, bool phase);
+int persist_default_block(int n, int *variant);
+size_t persist_lds_bytes(const PersistCfg &cfg);
+hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo *robots, const int32_t *list,
+                             int count, int grid, Planes pl, float4 *x, float4 *v, const float2 *sc,
+                             int n_steps, uint8_t *diverged, SimConst c, hipStream_t st);
+
+hipError_t launch_fitness(const RobotInfo *robots, int R, const float4 *x, const float4 *x0,
+                          const uint8_t *diverged, float *fit, hipStream_t st);
+
+hipError_t launch_gather_state(const RobotInfo *robots, int R, int total_slots, const int32_t *slot_robot,
+                               const int32_t *slot_node, const int64_t *mass_off, const float4 *x,
+                               const float4 *v, float *xo, float *vo, int scatter, hipStream_t st);
+
+hipError_t launch_springs_io(const RobotInfo *robots, int R, int total_slots, const int32_t *slot_robot,
+                             const int32_t *slot_node, const int32_t *sid, const int64_t *spring_off,
+                             Planes pl, float voxel_len, int32_t *ij, float *L0, float *k, float *a,
+                             float *phi, const float *k_in, const float *a_in, const float *phi_in,
+                             int write, hipStream_t st);
+
+}  // namespace sr

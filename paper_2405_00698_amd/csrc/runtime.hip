@@ -1,0 +1,518 @@
+// runtime.hip -- population handle, memory plan and the C ABI of softrobot.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sr;
+
+namespace {
+thread_local std::string g_err;
+
+int set_err(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+}  // namespace
+
+struct SideGroup {
+    int n, offset, count;
+    PersistCfg cfg;
+};
+
+struct sr_pop {
+    sr_sim_params p;
+    SimConst c;
+    hipStream_t st = nullptr;
+    int R = 0, max_side = 0;
+    std::vector<RobotInfo> h_robots;
+    RobotInfo *d_robots = nullptr;
+    int total_slots = 0, total_vox = 0;
+    uint8_t *kept = nullptr;
+    float *w = nullptr;
+    Planes pl{};
+    int32_t *sid = nullptr;
+    float4 *x0 = nullptr, *xbuf[2] = {nullptr, nullptr}, *vbuf[2] = {nullptr, nullptr};
+    int cur = 0;
+    int32_t *slot_node = nullptr, *node_slot = nullptr, *slot_robot = nullptr;
+    NodeRow *rows = nullptr;
+    Entry *entries = nullptr;
+    uint8_t *bad_class = nullptr, *diverged = nullptr;
+    int64_t *d_step = nullptr;
+    int64_t h_step = 0, h_step_stage = 0;
+    float2 *sc = nullptr;
+    int sc_cap = 0;
+    int32_t *d_lists = nullptr;
+    std::vector<SideGroup> groups;
+    int64_t *d_mass_off = nullptr, *d_spring_off = nullptr;
+    std::vector<int64_t> h_mass_off, h_spring_off;
+    bool counts_valid = false;
+    bool built = false;
+    bool phase = false;
+    int mode = SR_STEP_AUTO, spl = 0;
+    int sticky = 0;
+    // genome query scratch
+    uint8_t *q_cls = nullptr;
+    float *q_w = nullptr;
+};
+
+namespace {
+
+int fail_hip(sr_pop *pop, hipError_t e, const char *what) {
+    if (pop) pop->sticky = SR_EHIP;
+    return set_err(SR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPC(pop, x)                                         \
+    do {                                                     \
+        hipError_t e_ = (x);                                 \
+        if (e_ != hipSuccess) return fail_hip(pop, e_, #x);  \
+    } while (0)
+
+#define CHECK_POP(pop)                                                                    \
+    do {                                                                                  \
+        if (!(pop)) return set_err(SR_EINVAL, "null population handle");                  \
+        if ((pop)->sticky) return set_err((pop)->sticky, "population is in an error state"); \
+    } while (0)
+
+template <class T>
+hipError_t dalloc(T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
+}
+
+void pop_free(sr_pop *pop) {
+    void *ptrs[] = {pop->d_robots, pop->kept, pop->w, pop->pl.k, pop->pl.kL0, pop->pl.kal, pop->pl.kbe,
+                    pop->sid, pop->x0, pop->xbuf[0], pop->xbuf[1], pop->vbuf[0], pop->vbuf[1],
+                    pop->slot_node, pop->node_slot, pop->slot_robot, pop->rows, pop->entries,
+                    pop->bad_class, pop->diverged, pop->d_step, pop->sc, pop->d_lists, pop->d_mass_off,
+                    pop->d_spring_off, pop->q_cls, pop->q_w};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+int ensure_counts(sr_pop *pop) {
+    if (pop->counts_valid) return SR_OK;
+    HIPC(pop, hipMemcpyAsync(pop->h_robots.data(), pop->d_robots, sizeof(RobotInfo) * pop->R, hipMemcpyDeviceToHost,
+                             pop->st));
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    pop->h_mass_off.assign(pop->R + 1, 0);
+    pop->h_spring_off.assign(pop->R + 1, 0);
+    for (int r = 0; r < pop->R; ++r) {
+        pop->h_mass_off[r + 1] = pop->h_mass_off[r] + pop->h_robots[r].M;
+        pop->h_spring_off[r + 1] = pop->h_spring_off[r] + pop->h_robots[r].S;
+    }
+    HIPC(pop, hipMemcpyAsync(pop->d_mass_off, pop->h_mass_off.data(), sizeof(int64_t) * (pop->R + 1),
+                             hipMemcpyHostToDevice, pop->st));
+    HIPC(pop, hipMemcpyAsync(pop->d_spring_off, pop->h_spring_off.data(), sizeof(int64_t) * (pop->R + 1),
+                             hipMemcpyHostToDevice, pop->st));
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    pop->counts_valid = true;
+    return SR_OK;
+}
+
+int ensure_sc(sr_pop *pop, int n) {
+    if (n <= pop->sc_cap) return SR_OK;
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    if (pop->sc) HIPC(pop, hipFree(pop->sc));
+    pop->sc = nullptr;
+    int cap = n < 1024 ? 1024 : n;
+    HIPC(pop, dalloc(&pop->sc, (size_t)cap));
+    pop->sc_cap = cap;
+    return SR_OK;
+}
+
+// Runs after any build: resets step, buffers and cached counts.
+int finish_build(sr_pop *pop) {
+    pop->cur = 0;
+    HIPC(pop, hipMemcpyAsync(pop->xbuf[1], pop->xbuf[0], sizeof(float4) * pop->total_slots, hipMemcpyDeviceToDevice,
+                             pop->st));
+    HIPC(pop, hipMemcpyAsync(pop->vbuf[1], pop->vbuf[0], sizeof(float4) * pop->total_slots, hipMemcpyDeviceToDevice,
+                             pop->st));
+    pop->h_step = 0;
+    pop->h_step_stage = 0;
+    HIPC(pop, hipMemcpyAsync(pop->d_step, &pop->h_step_stage, sizeof(int64_t), hipMemcpyHostToDevice, pop->st));
+    uint8_t bad_host[1] = {0};
+    (void)bad_host;
+    std::vector<uint8_t> bad(pop->R);
+    HIPC(pop, hipMemcpyAsync(bad.data(), pop->bad_class, pop->R, hipMemcpyDeviceToHost, pop->st));
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    pop->counts_valid = false;
+    for (int r = 0; r < pop->R; ++r)
+        if (bad[r]) {
+            pop->built = false;
+            HIPC(pop, hipMemsetAsync(pop->bad_class, 0, pop->R, pop->st));
+            return set_err(SR_EINVAL, "robot %d has a voxel class outside 0..4", r);
+        }
+    pop->built = true;
+    return SR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sr_last_error(void) { return g_err.c_str(); }
+
+int sr_version(void) { return 1; }
+
+int sr_default_params(sr_sim_params *out) {
+    if (!out) return set_err(SR_EINVAL, "null output");
+    memset(out, 0, sizeof *out);
+    out->dt = 1e-4;
+    out->gravity = 9.81f;
+    out->damping = 0.999f;
+    out->mass = 0.1f;
+    out->voxel_len = 0.1f;
+    out->k_ground = 1e5f;
+    out->mu = 0.5f;
+    out->act_freq = 4.0f;
+    const float kc[5] = {0.f, 1e4f, 1e4f, 3e3f, 3e4f};
+    const float ac[5] = {0.f, 0.2f, -0.2f, 0.f, 0.f};
+    for (int c = 0; c < 5; ++c) {
+        out->k_class[c] = kc[c];
+        out->a_class[c] = ac[c];
+        out->phi_class[c] = 0.f;
+    }
+    out->flags = 0;
+    return SR_OK;
+}
+
+int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *grid_side, void *stream, sr_pop **out) {
+    if (!params || !grid_side || !out) return set_err(SR_EINVAL, "null argument");
+    *out = nullptr;
+    if (n_robots < 1) return set_err(SR_EINVAL, "n_robots must be >= 1 (got %d)", n_robots);
+    if (!(params->dt > 0) || !(params->mass > 0) || !(params->voxel_len > 0))
+        return set_err(SR_EINVAL, "dt, mass and voxel_len must be positive");
+    for (int r = 0; r < n_robots; ++r)
+        if (grid_side[r] < 1 || grid_side[r] > SR_MAX_SIDE)
+            return set_err(SR_EINVAL, "grid_side[%d] = %d outside 1..%d", r, grid_side[r], SR_MAX_SIDE);
+    sr_pop *pop = new sr_pop();
+    pop->p = *params;
+    pop->c = make_sim_const(*params);
+    pop->st = reinterpret_cast<hipStream_t>(stream);
+    pop->R = n_robots;
+    pop->h_robots.resize(n_robots);
+    int64_t slots = 0, vox = 0;
+    std::map<int, std::vector<int>> by_side;
+    for (int r = 0; r < n_robots; ++r) {
+        RobotInfo &ri = pop->h_robots[r];
+        ri.n = grid_side[r];
+        ri.N = ri.n + 1;
+        ri.slots = ri.N * ri.N * ri.N;
+        ri.slot_base = (int32_t)slots;
+        ri.vox_base = (int32_t)vox;
+        ri.M = 0;
+        ri.S = 0;
+        ri.pad = 0;
+        slots += ri.slots;
+        vox += (int64_t)ri.n * ri.n * ri.n;
+        by_side[ri.n].push_back(r);
+        if (ri.n > pop->max_side) pop->max_side = ri.n;
+    }
+    if (slots * 2 * NDIR >= INT32_MAX) {
+        delete pop;
+        return set_err(SR_EINVAL, "population too large for 32-bit slot indexing");
+    }
+    for (int c = 0; c < 5; ++c)
+        if (params->phi_class[c] != 0.f) pop->phase = true;
+    pop->total_slots = (int)slots;
+    pop->total_vox = (int)vox;
+    const size_t S = slots, P = slots * NDIR;
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, cnt) \
+    if (e == hipSuccess) e = dalloc(&(ptr), (cnt))
+    ALLOC(pop->d_robots, (size_t)n_robots);
+    ALLOC(pop->kept, (size_t)vox);
+    ALLOC(pop->w, (size_t)vox);
+    ALLOC(pop->pl.k, P);
+    ALLOC(pop->pl.kL0, P);
+    ALLOC(pop->pl.kal, P);
+    ALLOC(pop->pl.kbe, P);
+    ALLOC(pop->sid, P);
+    ALLOC(pop->x0, S);
+    ALLOC(pop->xbuf[0], S);
+    ALLOC(pop->xbuf[1], S);
+    ALLOC(pop->vbuf[0], S);
+    ALLOC(pop->vbuf[1], S);
+    ALLOC(pop->slot_node, S);
+    ALLOC(pop->node_slot, S);
+    ALLOC(pop->slot_robot, S);
+    ALLOC(pop->rows, S);
+    ALLOC(pop->entries, 2 * P);
+    ALLOC(pop->bad_class, (size_t)n_robots);
+    ALLOC(pop->diverged, (size_t)n_robots);
+    ALLOC(pop->d_step, 1);
+    ALLOC(pop->d_lists, (size_t)n_robots);
+    ALLOC(pop->d_mass_off, (size_t)n_robots + 1);
+    ALLOC(pop->d_spring_off, (size_t)n_robots + 1);
+    ALLOC(pop->q_cls, (size_t)vox);
+    ALLOC(pop->q_w, (size_t)vox);
+#undef ALLOC
+    if (e != hipSuccess) {
+        pop_free(pop);
+        delete pop;
+        return set_err(e == hipErrorOutOfMemory ? SR_ENOMEM : SR_EHIP, "allocation failed: %s", hipGetErrorString(e));
+    }
+    std::vector<int32_t> slot_robot(S);
+    for (int r = 0; r < n_robots; ++r)
+        for (int s = 0; s < pop->h_robots[r].slots; ++s) slot_robot[pop->h_robots[r].slot_base + s] = r;
+    std::vector<int32_t> lists;
+    for (auto &kv : by_side) {
+        SideGroup g;
+        g.n = kv.first;
+        g.offset = (int)lists.size();
+        g.count = (int)kv.second.size();
+        g.cfg.n = kv.first;
+        g.cfg.block = persist_default_block(kv.first, &g.cfg.variant);
+        lists.insert(lists.end(), kv.second.begin(), kv.second.end());
+        pop->groups.push_back(g);
+    }
+    int rc = SR_OK;
+    e = hipMemcpyAsync(pop->d_robots, pop->h_robots.data(), sizeof(RobotInfo) * n_robots, hipMemcpyHostToDevice,
+                       pop->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pop->slot_robot, slot_robot.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, pop->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pop->d_lists, lists.data(), sizeof(int32_t) * n_robots, hipMemcpyHostToDevice, pop->st);
+    if (e == hipSuccess) e = hipMemsetAsync(pop->bad_class, 0, n_robots, pop->st);
+    if (e == hipSuccess) e = hipMemsetAsync(pop->diverged, 0, n_robots, pop->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(pop->st);
+    if (e != hipSuccess) rc = set_err(SR_EHIP, "create: %s", hipGetErrorString(e));
+    if (rc != SR_OK) {
+        pop_free(pop);
+        delete pop;
+        return rc;
+    }
+    *out = pop;
+    return SR_OK;
+}
+
+int pop_destroy(sr_pop *pop) {
+    if (!pop) return SR_OK;
+    (void)hipStreamSynchronize(pop->st);
+    pop_free(pop);
+    delete pop;
+    return SR_OK;
+}
+
+int pop_build_from_voxels(sr_pop *pop, const uint8_t *cls, const float *w) {
+    CHECK_POP(pop);
+    if (!cls || !w) return set_err(SR_EINVAL, "null voxel array");
+    if (cls != pop->q_cls)
+        HIPC(pop, hipMemcpyAsync(pop->q_cls, cls, pop->total_vox, hipMemcpyDeviceToDevice, pop->st));
+    HIPC(pop, hipMemcpyAsync(pop->w, w, sizeof(float) * pop->total_vox, hipMemcpyDeviceToDevice, pop->st));
+    HIPC(pop, launch_build_mesh(pop->d_robots, pop->R, SR_MAX_SIDE, pop->p, cls, pop->w, pop->kept, pop->pl, pop->sid,
+                                pop->x0, pop->xbuf[0], pop->vbuf[0], pop->slot_node, pop->node_slot, pop->rows,
+                                pop->entries, pop->bad_class, pop->diverged, pop->st));
+    return finish_build(pop);
+}
+
+int pop_build_from_genomes(sr_pop *pop, const float *genomes, const float *B, int32_t precision) {
+    CHECK_POP(pop);
+    if (!genomes || !B) return set_err(SR_EINVAL, "null genome or B");
+    if (precision != SR_QUERY_FP32 && precision != SR_QUERY_BF16)
+        return set_err(SR_EINVAL, "unknown query precision %d", precision);
+    HIPC(pop, launch_query(pop->d_robots, pop->R, pop->max_side, genomes, B, precision, pop->q_cls, pop->q_w, pop->st));
+    return pop_build_from_voxels(pop, pop->q_cls, pop->q_w);
+}
+
+int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_per_launch) {
+    CHECK_POP(pop);
+    if (mode < SR_STEP_AUTO || mode > SR_STEP_PLAIN) return set_err(SR_EINVAL, "unknown step mode %d", mode);
+    pop->mode = mode;
+    pop->spl = steps_per_launch > 0 ? steps_per_launch : 0;
+    if (block > 0) {
+        for (auto &g : pop->groups) {
+            bool found = false;
+            for (int var : {1, 5, 2, 6, 0, 4}) {
+                PersistCfg c{g.n, block, var};
+                if (persist_supported(c, pop->phase)) {
+                    g.cfg = c;
+                    found = true;
+                    break;
+                }
+            }
+            if (!found) return set_err(SR_EUNSUPPORTED, "no persistent kernel for n=%d block=%d", g.n, block);
+        }
+    }
+    return SR_OK;
+}
+
+int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t variant) {
+    CHECK_POP(pop);
+    for (auto &g : pop->groups)
+        if (g.n == n) {
+            PersistCfg c{n, block, variant};
+            if (!persist_supported(c, pop->phase))
+                return set_err(SR_EUNSUPPORTED, "no persistent kernel for n=%d block=%d variant=%d", n, block, variant);
+            g.cfg = c;
+            return SR_OK;
+        }
+    return set_err(SR_EINVAL, "no robot of side %d", n);
+}
+
+int pop_step(sr_pop *pop, int32_t n_steps) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_step before a build");
+    if (n_steps < 0) return set_err(SR_EINVAL, "n_steps < 0");
+    if (n_steps == 0) return SR_OK;
+    int rc = ensure_sc(pop, n_steps);
+    if (rc) return rc;
+    const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
+    HIPC(pop, launch_sincos(pop->sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, pop->st));
+    if (pop->mode == SR_STEP_PLAIN) {
+        for (int t = 0; t < n_steps; ++t) {
+            const int a = pop->cur, b = 1 - pop->cur;
+            HIPC(pop, launch_plain_step(pop->d_robots, pop->R, pop->total_slots, pop->rows, pop->entries, pop->pl,
+                                        pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], pop->sc, t,
+                                        pop->phase, pop->diverged, pop->slot_robot, pop->c, pop->st));
+            pop->cur = b;
+        }
+        HIPC(pop, launch_check_div(pop->d_robots, pop->R, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->diverged,
+                                   pop->c.lim, pop->st));
+    } else {
+        const int spl = pop->spl > 0 ? pop->spl : n_steps;
+        for (int t0 = 0; t0 < n_steps; t0 += spl) {
+            const int cnt = (n_steps - t0) < spl ? (n_steps - t0) : spl;
+            for (const auto &g : pop->groups) {
+                HIPC(pop, launch_persistent(g.cfg, pop->phase, pop->d_robots, pop->d_lists + g.offset, g.count,
+                                            g.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->sc + t0,
+                                            cnt, pop->diverged, pop->c, pop->st));
+            }
+        }
+    }
+    HIPC(pop, launch_advance(pop->d_step, n_steps, pop->st));
+    pop->h_step += n_steps;
+    return SR_OK;
+}
+
+int pop_fitness(sr_pop *pop, float *fitness) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_fitness before a build");
+    if (!fitness) return set_err(SR_EINVAL, "null fitness");
+    HIPC(pop, launch_fitness(pop->d_robots, pop->R, pop->xbuf[pop->cur], pop->x0, pop->diverged, fitness, pop->st));
+    return SR_OK;
+}
+
+int pop_get_counts(sr_pop *pop, int32_t *n_masses, int32_t *n_springs, int64_t *mass_offset, int64_t *spring_offset) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_get_counts before a build");
+    int rc = ensure_counts(pop);
+    if (rc) return rc;
+    for (int r = 0; r < pop->R; ++r) {
+        if (n_masses) n_masses[r] = pop->h_robots[r].M;
+        if (n_springs) n_springs[r] = pop->h_robots[r].S;
+    }
+    if (mass_offset) memcpy(mass_offset, pop->h_mass_off.data(), sizeof(int64_t) * (pop->R + 1));
+    if (spring_offset) memcpy(spring_offset, pop->h_spring_off.data(), sizeof(int64_t) * (pop->R + 1));
+    return SR_OK;
+}
+
+int pop_get_voxels(sr_pop *pop, uint8_t *kept, float *w) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_get_voxels before a build");
+    if (kept) HIPC(pop, hipMemcpyAsync(kept, pop->kept, pop->total_vox, hipMemcpyDeviceToDevice, pop->st));
+    if (w) HIPC(pop, hipMemcpyAsync(w, pop->w, sizeof(float) * pop->total_vox, hipMemcpyDeviceToDevice, pop->st));
+    return SR_OK;
+}
+
+int pop_get_query(sr_pop *pop, uint8_t *cls, float *w) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_get_query before a build");
+    if (cls) HIPC(pop, hipMemcpyAsync(cls, pop->q_cls, pop->total_vox, hipMemcpyDeviceToDevice, pop->st));
+    if (w) HIPC(pop, hipMemcpyAsync(w, pop->w, sizeof(float) * pop->total_vox, hipMemcpyDeviceToDevice, pop->st));
+    return SR_OK;
+}
+
+int pop_get_springs(sr_pop *pop, int32_t *ij, float *L0, float *k, float *a, float *phi) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_get_springs before a build");
+    int rc = ensure_counts(pop);
+    if (rc) return rc;
+    HIPC(pop, launch_springs_io(pop->d_robots, pop->R, pop->total_slots, pop->slot_robot, pop->slot_node, pop->sid,
+                                pop->d_spring_off, pop->pl, pop->p.voxel_len, ij, L0, k, a, phi, nullptr, nullptr,
+                                nullptr, 0, pop->st));
+    return SR_OK;
+}
+
+int pop_set_spring_params(sr_pop *pop, const float *k, const float *a, const float *phi) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_set_spring_params before a build");
+    int rc = ensure_counts(pop);
+    if (rc) return rc;
+    if (phi) pop->phase = true;
+    HIPC(pop, launch_springs_io(pop->d_robots, pop->R, pop->total_slots, pop->slot_robot, pop->slot_node, pop->sid,
+                                pop->d_spring_off, pop->pl, pop->p.voxel_len, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, k, a, phi, 1, pop->st));
+    return SR_OK;
+}
+
+int pop_get_state(sr_pop *pop, float *x, float *v, int64_t *step) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_get_state before a build");
+    int rc = ensure_counts(pop);
+    if (rc) return rc;
+    HIPC(pop, launch_gather_state(pop->d_robots, pop->R, pop->total_slots, pop->slot_robot, pop->slot_node,
+                                  pop->d_mass_off, pop->xbuf[pop->cur], pop->vbuf[pop->cur], x, v, 0, pop->st));
+    if (step) *step = pop->h_step;
+    return SR_OK;
+}
+
+int pop_set_state(sr_pop *pop, const float *x, const float *v, int64_t step) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_set_state before a build");
+    if (step < 0) return set_err(SR_EINVAL, "step < 0");
+    int rc = ensure_counts(pop);
+    if (rc) return rc;
+    HIPC(pop, launch_gather_state(pop->d_robots, pop->R, pop->total_slots, pop->slot_robot, pop->slot_node,
+                                  pop->d_mass_off, pop->xbuf[pop->cur], pop->vbuf[pop->cur], const_cast<float *>(x),
+                                  const_cast<float *>(v), 1, pop->st));
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    pop->h_step = step;
+    pop->h_step_stage = step;
+    HIPC(pop, hipMemcpyAsync(pop->d_step, &pop->h_step_stage, sizeof(int64_t), hipMemcpyHostToDevice, pop->st));
+    HIPC(pop, hipMemsetAsync(pop->diverged, 0, pop->R, pop->st));
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    return SR_OK;
+}
+
+int pop_get_status(sr_pop *pop, uint8_t *diverged) {
+    CHECK_POP(pop);
+    if (!diverged) return set_err(SR_EINVAL, "null output");
+    HIPC(pop, hipMemcpyAsync(diverged, pop->diverged, pop->R, hipMemcpyDeviceToDevice, pop->st));
+    return SR_OK;
+}
+
+int ga_generation(const float *fitness, const float *genomes_in, float *genomes_out, int32_t P, int32_t L,
+                  const sr_ga_params *params, uint64_t seed, uint64_t generation, int32_t *decisions, void *stream) {
+    if (!fitness || !genomes_in || !genomes_out || !params) return set_err(SR_EINVAL, "null argument");
+    if (P < 1 || L < 1) return set_err(SR_EINVAL, "P and L must be >= 1 (got %d, %d)", P, L);
+    if (params->tournament_k < 1 || params->tournament_k > 64)
+        return set_err(SR_EINVAL, "tournament_k %d outside 1..64", params->tournament_k);
+    if (!(params->elite_frac >= 0.0 && params->elite_frac <= 1.0))
+        return set_err(SR_EINVAL, "elite_frac outside [0, 1]");
+    const char *a0 = reinterpret_cast<const char *>(genomes_in), *b0 = reinterpret_cast<const char *>(genomes_out);
+    const size_t bytes = sizeof(float) * (size_t)P * (size_t)L;
+    if (a0 < b0 + bytes && b0 < a0 + bytes) return set_err(SR_EINVAL, "genomes_out overlaps genomes_in");
+    int E = (int)floor(params->elite_frac * (double)P);
+    if (E > P) E = P;
+    hipError_t e = launch_ga(fitness, genomes_in, genomes_out, P, L, E, params->tournament_k, params->p_cross_thr,
+                             params->p_mut_thr, params->mut_sigma, seed, generation, decisions,
+                             reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return set_err(SR_EHIP, "ga_generation: %s", hipGetErrorString(e));
+    return SR_OK;
+}
+
+}  // extern "C"

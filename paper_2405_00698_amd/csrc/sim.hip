@@ -1,0 +1,594 @@
+// sim.hip -- time stepping (per-step and persistent forms), fitness, state I/O.
+#include "spring.h"
+
+namespace sr {
+
+SimConst make_sim_const(const sr_sim_params &p) {
+    SimConst c;
+    c.dt = (float)p.dt;
+    c.dt_m = (float)(p.dt / (double)p.mass);
+    c.damping = p.damping;
+    c.mg = (float)((double)p.mass * (double)p.gravity);
+    c.kc = p.k_ground;
+    c.mu_kc_dt_m = (float)((double)p.mu * (double)p.k_ground * p.dt / (double)p.mass);
+    c.lim = (float)(1e3 * (double)p.voxel_len);
+    // the same float products the mesh build uses for k * L0
+    c.L0e = p.voxel_len * sqrtf(1.0f);
+    c.L0f = p.voxel_len * sqrtf(2.0f);
+    c.L0b = p.voxel_len * sqrtf(3.0f);
+    c.gravity = !(p.flags & SR_NO_GRAVITY);
+    c.ground = !(p.flags & SR_NO_GROUND);
+    c.actuation = !(p.flags & SR_NO_ACTUATION);
+    return c;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- time table
+// (sin, cos)(w t_n) for the steps of one call, t_n = n dt from the integer n.
+// Without actuation the table is zero, so k L(t) = kL0.
+__global__ void k_sincos(float2 *sc, const int64_t *d_step, int n, double omega_dt, int on) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!on) {
+        sc[i] = make_float2(0.f, 0.f);
+        return;
+    }
+    const double arg = omega_dt * (double)(*d_step + i);
+    double s, c;
+    sincos(arg, &s, &c);
+    sc[i] = make_float2((float)s, (float)c);
+}
+
+__global__ void k_advance(int64_t *d_step, int n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += n;
+}
+
+// ---------------------------------------------------------------- per-step form
+// One thread per node; positions and velocities in HBM, one launch per step.
+// The node gathers over its incidence row (forward springs, then backward
+// springs), recomputing every spring force it touches.
+template <bool PHASE>
+__global__ __launch_bounds__(256) void k_plain(const RobotInfo *robots, int total_slots, const int32_t *slot_robot,
+                                               const NodeRow *rows, const Entry *entries, Planes pl,
+                                               const float4 *__restrict__ x, const float4 *__restrict__ v,
+                                               float4 *__restrict__ xn, float4 *__restrict__ vn,
+                                               const float2 *sc_tab, int t, const uint8_t *diverged, SimConst c) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const float2 sc = sc_tab[t];
+    if (g >= total_slots) return;
+    const int r = slot_robot[g];
+    const RobotInfo ri = robots[r];
+    if (g - ri.slot_base >= ri.M || diverged[r]) return;
+    const NodeRow row = rows[g];
+    const float4 X = x[row.gslot];
+    float3 Ff = make_float3(0.f, 0.f, 0.f), Fb = make_float3(0.f, 0.f, 0.f);
+    for (int e = row.start; e < row.mid; ++e) {
+        const Entry E = entries[e];
+        const float4 Y = x[E.nbr];
+        const float dx = Y.x - X.x, dy = Y.y - X.y, dz = Y.z - X.z;
+        const float cf = spring_coef<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane],
+                                            PHASE ? pl.kbe[E.plane] : 0.f, sc.x, sc.y, len2(dx, dy, dz));
+        Ff.x = fmaf(cf, dx, Ff.x);
+        Ff.y = fmaf(cf, dy, Ff.y);
+        Ff.z = fmaf(cf, dz, Ff.z);
+    }
+    for (int e = row.mid; e < row.end; ++e) {
+        const Entry E = entries[e];
+        const float4 Y = x[E.nbr];
+        const float dx = Y.x - X.x, dy = Y.y - X.y, dz = Y.z - X.z;
+        const float cf = spring_coef<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane],
+                                            PHASE ? pl.kbe[E.plane] : 0.f, sc.x, sc.y, len2(dx, dy, dz));
+        Fb.x = fmaf(cf, dx, Fb.x);
+        Fb.y = fmaf(cf, dy, Fb.y);
+        Fb.z = fmaf(cf, dz, Fb.z);
+    }
+    float3 xs = make_float3(X.x, X.y, X.z);
+    const float4 V = v[row.gslot];
+    float3 vs = make_float3(V.x, V.y, V.z);
+    integrate_node(c, xs, vs, Ff, Fb);
+    xn[row.gslot] = make_float4(xs.x, xs.y, xs.z, 1.f);
+    vn[row.gslot] = make_float4(vs.x, vs.y, vs.z, 0.f);
+}
+
+__global__ __launch_bounds__(256) void k_check_div(const RobotInfo *robots, const float4 *x, const float4 *v,
+                                                   uint8_t *diverged, float lim_per_side) {
+    __shared__ int bad;
+    const RobotInfo ri = robots[blockIdx.x];
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const float lim = lim_per_side * ri.n;
+    for (int s = threadIdx.x; s < ri.slots; s += blockDim.x) {
+        const float4 X = x[ri.slot_base + s], V = v[ri.slot_base + s];
+        if (X.w != 0.f && node_bad(make_float3(X.x, X.y, X.z), make_float3(V.x, V.y, V.z), lim)) bad = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && bad) diverged[blockIdx.x] = 1;
+}
+
+// ---------------------------------------------------------------- persistent form
+// One workgroup holds one robot for a whole block of steps.  Positions sit in
+// LDS as float4 on the dense (n+1)^3 lattice (double-buffered, with ghost
+// padding so every stencil neighbour address is in range); velocities and
+// spring parameters sit in VGPRs.  Each thread owns NPT lattice slots.
+//
+// Force assembly per step (all in a fixed order, no atomics):
+//  - variant 1/2 (exchange): a slot computes the spring coefficient of each of
+//    its 13 forward springs once, adds its share to its own forward sum and
+//    writes the coefficient to LDS at its own index; after a barrier the upper
+//    endpoint reads the coefficient of each of its 13 backward springs at the
+//    lower slot's index and adds coef * (x_lower - x_self).  The coefficient
+//    rows have PAD zero entries in front, which stand for the missing lower
+//    neighbours of the first slots and are never written.  Variant 2 does this
+//    in two direction chunks to halve the LDS buffer.
+//  - variant 0 (recompute): the upper endpoint recomputes the coefficient
+//    itself from the lower slot's parameters (held in its own VGPRs).
+// All variants produce identical bits: each coefficient is computed from the
+// same operands with the same operations.
+struct PArgs {
+    const RobotInfo *robots;
+    const int32_t *list;
+    int count;
+    Planes pl;
+    float4 *x, *v;
+    const float2 *sc;
+    int n_steps;
+    uint8_t *diverged;
+    SimConst c;
+};
+
+template <int N>
+struct Geo {
+    static constexpr int SL = N * N * N;
+    static constexpr int PAD = N * N + N + 1;
+    static constexpr int XL = SL + 2 * PAD;
+    static constexpr int CL = SL + PAD;
+};
+
+template <int N, int BS, int VAR>
+constexpr size_t lds_bytes() {
+    using G = Geo<N>;
+    constexpr int NDC = VAR == 0 ? 0 : (NDIR + VAR - 1) / VAR;
+    return 2 * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL;
+}
+
+template <int N, int BS, int VAR, bool FENCE, bool PHASE>
+__global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    using G = Geo<N>;
+    constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
+    constexpr int NPT = (SL + BS - 1) / BS;
+    constexpr int NCH = VAR == 0 ? 1 : VAR;
+    constexpr int NDC = VAR == 0 ? 0 : (NDIR + VAR - 1) / VAR;
+    constexpr int NQ = VAR == 0 ? NDIR : 1;  // backward parameter copies (recompute variant)
+    constexpr int NB = PHASE ? NDIR : 1;
+    // three distinct LDS objects, so the compiler knows coefficient stores
+    // never alias position loads and can keep many loads in flight
+    __shared__ float4 xb0[XL];
+    __shared__ float4 xb1[XL];
+    __shared__ float coef[NDC > 0 ? NDC * CL : 1];
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const SimConst c = A.c;
+
+    for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
+        const int r = A.list[q];
+        if (A.diverged[r]) continue;
+        const int base = A.robots[r].slot_base;
+        const int pbase = NDIR * base;
+        const float lim = c.lim * (N - 1);
+
+        if (VAR != 0)
+            for (int i = tid; i < NDC * CL; i += BS) coef[i] = 0.f;
+        const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f);
+        for (int i = tid; i < PAD; i += BS) {
+            xb0[i] = ghost;
+            xb1[i] = ghost;
+            xb0[PAD + SL + i] = ghost;
+            xb1[PAD + SL + i] = ghost;
+        }
+        if (tid == 0) bad = 0;
+
+        float3 xr[NPT], vr[NPT];
+        bool pres[NPT];
+        float pk[NPT][NDIR], pa[NPT][NDIR], pb[NPT][NB];
+        float qk[NPT][NQ], qa[NPT][NQ], qb[NPT][NQ];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            const bool live = s < SL;
+            const int sc_ = live ? s : 0;
+            const float4 X = A.x[base + sc_];
+            const float4 V = A.v[base + sc_];
+            if (live) {
+                xb0[PAD + s] = X;
+                xb1[PAD + s] = X;
+            }
+            xr[k] = make_float3(X.x, X.y, X.z);
+            vr[k] = make_float3(V.x, V.y, V.z);
+            pres[k] = live && X.w != 0.f;
+#pragma unroll
+            for (int d = 0; d < NDIR; ++d) {
+                const int pi = pbase + d * SL + sc_;
+                pk[k][d] = live ? A.pl.k[pi] : 0.f;
+                pa[k][d] = live ? A.pl.kal[pi] : 0.f;
+                if (PHASE) pb[k][d] = live ? A.pl.kbe[pi] : 0.f;
+            }
+            if (VAR == 0) {
+#pragma unroll
+                for (int d = 0; d < NQ; ++d) {
+                    const int lo = s - dir_off(d, N);
+                    const bool ok = live && lo >= 0;
+                    const int pi = pbase + d * SL + (ok ? lo : 0);
+                    qk[k][d] = ok ? A.pl.k[pi] : 0.f;
+                    qa[k][d] = ok ? A.pl.kal[pi] : 0.f;
+                    qb[k][d] = (ok && PHASE) ? A.pl.kbe[pi] : 0.f;
+                }
+            }
+        }
+        __syncthreads();
+
+        float2 sc_next = A.sc[0];
+        for (int t = 0; t < A.n_steps; ++t) {
+            const float2 sct = sc_next;
+            if (t + 1 < A.n_steps) sc_next = A.sc[t + 1];
+            const float4 *const xc = (t & 1) ? xb1 : xb0;
+            float4 *const xn = (t & 1) ? xb0 : xb1;
+            float3 Ff[NPT], Fb[NPT];
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                Ff[k] = make_float3(0.f, 0.f, 0.f);
+                Fb[k] = make_float3(0.f, 0.f, 0.f);
+            }
+            if (VAR == 0) {
+#pragma unroll
+                for (int k = 0; k < NPT; ++k) {
+                    const int s = tid + k * BS;
+                    if (s < SL) {
+#pragma unroll
+                        for (int d = 0; d < NDIR; ++d) {
+                            const float3 Y = ld3(xc + s + (PAD + dir_off(d, N)));
+                            const float dx = Y.x - xr[k].x, dy = Y.y - xr[k].y, dz = Y.z - xr[k].z;
+                            const float cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
+                                                                PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz));
+                            Ff[k].x = fmaf(cf, dx, Ff[k].x);
+                            Ff[k].y = fmaf(cf, dy, Ff[k].y);
+                            Ff[k].z = fmaf(cf, dz, Ff[k].z);
+                        }
+#pragma unroll
+                        for (int d = 0; d < NQ; ++d) {
+                            const float3 Y = ld3(xc + s + (PAD - dir_off(d, N)));
+                            const float ex = Y.x - xr[k].x, ey = Y.y - xr[k].y, ez = Y.z - xr[k].z;
+                            const float cf = spring_coef<PHASE>(qk[k][d], qk[k][d] * L0d(c, d), qa[k][d], qb[k][d],
+                                                                sct.x, sct.y, len2(ex, ey, ez));
+                            Fb[k].x = fmaf(cf, ex, Fb[k].x);
+                            Fb[k].y = fmaf(cf, ey, Fb[k].y);
+                            Fb[k].z = fmaf(cf, ez, Fb[k].z);
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int d0 = ch * NDC;
+                    const int d1 = (ch + 1) * NDC < NDIR ? (ch + 1) * NDC : NDIR;
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int s = tid + k * BS;
+                        if (s < SL) {
+                            // every neighbour read of this slot is issued before any use;
+                            // addresses are one base plus non-negative immediates
+                            const float4 *xs = xc + s;
+                            float *cs = coef + s;
+                            float3 Y[NDIR];
+#pragma unroll
+                            for (int d = d0; d < d1; ++d) Y[d] = ld3(xs + (PAD + dir_off(d, N)));
+                            float cfv[NDIR];
+#pragma unroll
+                            for (int d = d0; d < d1; ++d) {
+                                const float dx = Y[d].x - xr[k].x, dy = Y[d].y - xr[k].y, dz = Y[d].z - xr[k].z;
+                                const float cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
+                                                                    PHASE ? pb[k][d] : 0.f, sct.x, sct.y,
+                                                                    len2(dx, dy, dz));
+                                cfv[d] = cf;
+                                Ff[k].x = fmaf(cf, dx, Ff[k].x);
+                                Ff[k].y = fmaf(cf, dy, Ff[k].y);
+                                Ff[k].z = fmaf(cf, dz, Ff[k].z);
+                            }
+#pragma unroll
+                            for (int d = d0; d < d1; ++d) cs[(d - d0) * CL + PAD] = cfv[d];
+                        }
+                        if (FENCE) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int s = tid + k * BS;
+                        if (s < SL) {
+                            const float4 *xs = xc + s;
+                            const float *cs = coef + s;
+                            float3 Y[NDIR];
+                            float cfv[NDIR];
+#pragma unroll
+                            for (int d = d0; d < d1; ++d) {
+                                Y[d] = ld3(xs + (PAD - dir_off(d, N)));
+                                cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
+                            }
+#pragma unroll
+                            for (int d = d0; d < d1; ++d) {
+                                const float ex = Y[d].x - xr[k].x, ey = Y[d].y - xr[k].y, ez = Y[d].z - xr[k].z;
+                                Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
+                                Fb[k].y = fmaf(cfv[d], ey, Fb[k].y);
+                                Fb[k].z = fmaf(cfv[d], ez, Fb[k].z);
+                            }
+                        }
+                        if (FENCE) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if (ch + 1 < NCH) __syncthreads();
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int s = tid + k * BS;
+                if (pres[k]) {
+                    integrate_node(c, xr[k], vr[k], Ff[k], Fb[k]);
+                    xn[PAD + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
+                }
+            }
+            __syncthreads();
+        }
+
+        bool mybad = false;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            if (pres[k]) {
+                A.x[base + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
+                A.v[base + s] = make_float4(vr[k].x, vr[k].y, vr[k].z, 0.f);
+                mybad |= node_bad(xr[k], vr[k], lim);
+            }
+        }
+        if (mybad) bad = 1;
+        __syncthreads();
+        if (tid == 0 && bad) A.diverged[r] = 1;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- fitness
+__global__ __launch_bounds__(256) void k_fitness(const RobotInfo *robots, const float4 *x, const float4 *x0,
+                                                 const uint8_t *diverged, float *fit) {
+    __shared__ float part[4];
+    const RobotInfo ri = robots[blockIdx.x];
+    float s = 0.f;
+    for (int q = threadIdx.x; q < ri.slots; q += 256) {
+        const float4 X0 = x0[ri.slot_base + q];
+        if (X0.w != 0.f) s += x[ri.slot_base + q].x - X0.x;
+    }
+    // fixed-order wave tree, then waves in order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float tot = (part[0] + part[1]) + (part[2] + part[3]);
+        float f = ri.M > 0 ? tot / (float)ri.M : 0.f;
+        if (diverged[blockIdx.x] || !(fabsf(f) <= 3.0e38f)) f = -INFINITY;
+        fit[blockIdx.x] = f;
+    }
+}
+
+// ---------------------------------------------------------------- state / spring I/O
+__global__ void k_gather_state(const RobotInfo *robots, int total_slots, const int32_t *slot_robot,
+                               const int32_t *slot_node, const int64_t *mass_off, float4 *x, float4 *v, float *xo,
+                               float *vo, int scatter) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_slots) return;
+    const int id = slot_node[g];
+    if (id < 0) return;
+    const int64_t o = 3 * (mass_off[slot_robot[g]] + id);
+    if (!scatter) {
+        const float4 X = x[g], V = v[g];
+        if (xo) { xo[o] = X.x; xo[o + 1] = X.y; xo[o + 2] = X.z; }
+        if (vo) { vo[o] = V.x; vo[o + 1] = V.y; vo[o + 2] = V.z; }
+    } else {
+        if (xo) x[g] = make_float4(xo[o], xo[o + 1], xo[o + 2], 1.f);
+        if (vo) v[g] = make_float4(vo[o], vo[o + 1], vo[o + 2], 0.f);
+    }
+}
+
+__global__ void k_springs_io(const RobotInfo *robots, int total_slots, const int32_t *slot_robot,
+                             const int32_t *slot_node, const int32_t *sid, const int64_t *spring_off, Planes pl,
+                             float voxel_len, int32_t *ij, float *L0o, float *ko, float *ao, float *phio,
+                             const float *kin, const float *ain, const float *phin, int write) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_slots) return;
+    const int r = slot_robot[g];
+    const RobotInfo ri = robots[r];
+    const int s = g - ri.slot_base;
+    for (int d = 0; d < NDIR; ++d) {
+        const int pi = NDIR * ri.slot_base + d * ri.slots + s;
+        const int id = sid[pi];
+        if (id < 0) continue;
+        const int64_t o = spring_off[r] + id;
+        const float L0 = voxel_len * sqrtf((float)dir_len2(d));
+        if (!write) {
+            if (ij) {
+                ij[2 * o] = slot_node[g];
+                ij[2 * o + 1] = slot_node[g + dir_off(d, ri.N)];
+            }
+            if (L0o) L0o[o] = L0;
+            const float k = pl.k[pi], kL0 = pl.kL0[pi], kal = pl.kal[pi], kbe = pl.kbe[pi];
+            float a = 0.f, ph = 0.f;
+            if (kL0 != 0.f) {
+                if (kbe == 0.f) a = kal / kL0;
+                else {
+                    a = sqrtf(kal * kal + kbe * kbe) / kL0;
+                    ph = atan2f(kbe, kal);
+                }
+            }
+            if (ko) ko[o] = k;
+            if (ao) ao[o] = a;
+            if (phio) phio[o] = ph;
+        } else {
+            // read the current values for fields that are not given
+            float k = pl.k[pi], kL0 = pl.kL0[pi], kal = pl.kal[pi], kbe = pl.kbe[pi];
+            float a = 0.f, ph = 0.f;
+            if (kL0 != 0.f) {
+                if (kbe == 0.f) a = kal / kL0;
+                else {
+                    a = sqrtf(kal * kal + kbe * kbe) / kL0;
+                    ph = atan2f(kbe, kal);
+                }
+            }
+            if (kin) k = kin[o];
+            if (ain) a = ain[o];
+            if (phin) ph = phin[o];
+            pl.k[pi] = k;
+            pl.kL0[pi] = k * L0;
+            if (ph == 0.f) {
+                pl.kal[pi] = k * L0 * a;
+                pl.kbe[pi] = 0.f;
+            } else {
+                pl.kal[pi] = k * L0 * a * cosf(ph);
+                pl.kbe[pi] = k * L0 * a * sinf(ph);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- persistent dispatch table
+typedef void (*PersistFn)(PArgs);
+struct PersistEntry {
+    int n, block, variant;
+    PersistFn fn, fn_phase;
+    size_t lds;
+};
+
+// variant code: exchange variant (0, 1, 2) + 4 when scheduling fences bound the
+// number of LDS loads in flight (fewer registers, less latency hiding)
+#define SR_PE(NN, BS, VAR, F)                                                                     \
+    {                                                                                             \
+        NN, BS, VAR + 4 * F, k_persist<NN + 1, BS, VAR, F, false>, k_persist<NN + 1, BS, VAR, F, true>, \
+            lds_bytes<NN + 1, BS, VAR>()                                                          \
+    }
+
+// The first entry of each side is its default configuration.
+const PersistEntry kPersist[] = {
+    SR_PE(1, 64, 1, 0),   SR_PE(2, 64, 1, 0),   SR_PE(3, 64, 1, 0),    SR_PE(4, 128, 1, 0),  SR_PE(4, 64, 1, 0),
+    SR_PE(5, 256, 1, 0),  SR_PE(5, 128, 1, 0),  SR_PE(6, 384, 1, 0),   SR_PE(6, 192, 1, 0),  SR_PE(7, 512, 1, 0),
+    SR_PE(7, 256, 1, 0),  SR_PE(8, 768, 1, 0),  SR_PE(8, 384, 1, 0),   SR_PE(8, 256, 1, 0),  SR_PE(8, 768, 0, 0),
+    SR_PE(8, 384, 1, 1),  SR_PE(8, 256, 1, 1),  SR_PE(9, 1024, 1, 0),  SR_PE(9, 512, 1, 0),  SR_PE(9, 512, 1, 1),
+    SR_PE(10, 448, 1, 0), SR_PE(10, 448, 1, 1), SR_PE(10, 704, 1, 0),  SR_PE(10, 704, 1, 1), SR_PE(10, 1024, 1, 0),
+    SR_PE(10, 1024, 1, 1), SR_PE(10, 704, 0, 0), SR_PE(10, 704, 2, 0), SR_PE(10, 448, 2, 0), SR_PE(10, 448, 0, 0),
+    SR_PE(11, 896, 1, 0), SR_PE(11, 896, 1, 1), SR_PE(11, 576, 1, 0),  SR_PE(11, 576, 1, 1), SR_PE(12, 768, 2, 0),
+    SR_PE(12, 768, 2, 1), SR_PE(12, 768, 0, 0), SR_PE(12, 1024, 2, 0), SR_PE(12, 1024, 2, 1),
+};
+
+const PersistEntry *find_persist(const PersistCfg &cfg) {
+    for (const auto &e : kPersist)
+        if (e.n == cfg.n && e.block == cfg.block && e.variant == cfg.variant) return &e;
+    return nullptr;
+}
+
+}  // namespace
+
+bool persist_supported(const PersistCfg &cfg, bool phase) {
+    (void)phase;
+    const PersistEntry *e = find_persist(cfg);
+    return e && e->lds <= 160 * 1024;
+}
+
+size_t persist_lds_bytes(const PersistCfg &cfg) {
+    const PersistEntry *e = find_persist(cfg);
+    return e ? e->lds : 0;
+}
+
+int persist_default_block(int n, int *variant) {
+    for (const auto &e : kPersist)
+        if (e.n == n && e.lds <= 160 * 1024) {
+            *variant = e.variant;
+            return e.block;
+        }
+    return 0;
+}
+
+hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo *robots, const int32_t *list, int count,
+                             int grid, Planes pl, float4 *x, float4 *v, const float2 *sc, int n_steps,
+                             uint8_t *diverged, SimConst c, hipStream_t st) {
+    const PersistEntry *e = find_persist(cfg);
+    if (!e || e->lds > 160 * 1024) return hipErrorInvalidConfiguration;
+    PArgs A;
+    A.robots = robots;
+    A.list = list;
+    A.count = count;
+    A.pl = pl;
+    A.x = x;
+    A.v = v;
+    A.sc = sc;
+    A.n_steps = n_steps;
+    A.diverged = diverged;
+    A.c = c;
+    PersistFn fn = phase ? e->fn_phase : e->fn;
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(e->block), 0, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_sincos(float2 *sc, const int64_t *d_step, int n, double omega_dt, int on, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sincos, dim3((n + 255) / 256), dim3(256), 0, st, sc, d_step, n, omega_dt, on);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(int64_t *d_step, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, d_step, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_step(const RobotInfo *robots, int R, int total_slots, const NodeRow *rows, const Entry *entries,
+                             Planes pl, const float4 *x, const float4 *v, float4 *xn, float4 *vn, const float2 *sc,
+                             int t, bool phase, const uint8_t *diverged, const int32_t *slot_robot, SimConst c,
+                             hipStream_t st) {
+    (void)R;
+    if (phase)
+        hipLaunchKernelGGL(k_plain<true>, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots,
+                           slot_robot, rows, entries, pl, x, v, xn, vn, sc, t, diverged, c);
+    else
+        hipLaunchKernelGGL(k_plain<false>, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots,
+                           slot_robot, rows, entries, pl, x, v, xn, vn, sc, t, diverged, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_div(const RobotInfo *robots, int R, const float4 *x, const float4 *v, uint8_t *diverged,
+                            float lim, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_div, dim3(R), dim3(256), 0, st, robots, x, v, diverged, lim);
+    return hipGetLastError();
+}
+
+hipError_t launch_fitness(const RobotInfo *robots, int R, const float4 *x, const float4 *x0, const uint8_t *diverged,
+                          float *fit, hipStream_t st) {
+    hipLaunchKernelGGL(k_fitness, dim3(R), dim3(256), 0, st, robots, x, x0, diverged, fit);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_state(const RobotInfo *robots, int R, int total_slots, const int32_t *slot_robot,
+                               const int32_t *slot_node, const int64_t *mass_off, const float4 *x, const float4 *v,
+                               float *xo, float *vo, int scatter, hipStream_t st) {
+    (void)R;
+    hipLaunchKernelGGL(k_gather_state, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots,
+                       slot_robot, slot_node, mass_off, const_cast<float4 *>(x), const_cast<float4 *>(v), xo, vo,
+                       scatter);
+    return hipGetLastError();
+}
+
+hipError_t launch_springs_io(const RobotInfo *robots, int R, int total_slots, const int32_t *slot_robot,
+                             const int32_t *slot_node, const int32_t *sid, const int64_t *spring_off, Planes pl,
+                             float voxel_len, int32_t *ij, float *L0, float *k, float *a, float *phi,
+                             const float *k_in, const float *a_in, const float *phi_in, int write, hipStream_t st) {
+    (void)R;
+    hipLaunchKernelGGL(k_springs_io, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots,
+                       slot_robot, slot_node, sid, spring_off, pl, voxel_len, ij, L0, k, a, phi, k_in, a_in, phi_in,
+                       write);
+    return hipGetLastError();
+}
+
+}  // namespace sr

@@ -1,0 +1,75 @@
+// spring.h -- the per-spring force coefficient and the per-node update, shared
+// by the per-step kernel and the persistent kernel so that both produce the
+// same bits for the same state.
+#pragma once
+
+#include "internal.h"
+
+namespace sr {
+
+// Hooke spring with actuated rest length L(t) = L0 (1 + a sin(w t + phi)):
+// the force on the lower endpoint is k (r - L) d / r = (k - k L / r) d, with
+// d = x_upper - x_lower.  k L = kL0 + kal S + kbe C with (S, C) = (sin, cos)(w t).
+// Returns the scalar coefficient of d.  A collapsed spring (r^2 below 1e-30)
+// has no direction; the guard keeps 1/r finite so an absent spring (all
+// parameters zero) contributes an exact zero.
+template <bool PHASE>
+__device__ __forceinline__ float spring_coef(float k, float kL0, float kal, float kbe, float S, float C,
+                                             float r2) {
+    float kL = fmaf(kal, S, kL0);
+    if (PHASE) kL = fmaf(kbe, C, kL);
+    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+    return fmaf(-kL, ir, k);
+}
+
+// rest length of direction d: voxel edge times 1, sqrt 2 or sqrt 3
+__device__ __forceinline__ float L0d(const SimConst &c, int d) {
+    return dir_len2(d) == 1 ? c.L0e : dir_len2(d) == 2 ? c.L0f : c.L0b;
+}
+
+// xyz of a 16-byte aligned float4 slot, as one 12-byte LDS read
+typedef float f3v __attribute__((ext_vector_type(3)));
+__device__ __forceinline__ float3 ld3(const float4 *p) {
+    const f3v v = *reinterpret_cast<const f3v *>(__builtin_assume_aligned(p, 16));
+    return make_float3(v.x, v.y, v.z);
+}
+
+__device__ __forceinline__ float len2(float dx, float dy, float dz) { return fmaf(dz, dz, fmaf(dy, dy, dx * dx)); }
+
+// One node's update from its total spring force (forward-direction sum Ff and
+// backward-direction sum Fb, added in that order): gravity, ground normal,
+// semi-implicit Euler, velocity-level Coulomb friction, damping.
+__device__ __forceinline__ void integrate_node(const SimConst &c, float3 &x, float3 &v, float3 Ff, float3 Fb) {
+    float Fx = Ff.x + Fb.x, Fy = Ff.y + Fb.y, Fz = Ff.z + Fb.z;
+    const bool below = c.ground && x.z < 0.f;
+    if (c.gravity) Fz -= c.mg;
+    if (below) Fz = fmaf(c.kc, -x.z, Fz);
+    float vx = fmaf(c.dt_m, Fx, v.x), vy = fmaf(c.dt_m, Fy, v.y), vz = fmaf(c.dt_m, Fz, v.z);
+    if (below) {
+        const float dv = c.mu_kc_dt_m * (-x.z);
+        const float u = sqrtf(fmaf(vy, vy, vx * vx));
+        if (u <= dv) {
+            vx = 0.f;
+            vy = 0.f;
+        } else {
+            const float s = 1.f - dv / u;
+            vx *= s;
+            vy *= s;
+        }
+    }
+    v.x = c.damping * vx;
+    v.y = c.damping * vy;
+    v.z = c.damping * vz;
+    x.x = fmaf(c.dt, v.x, x.x);
+    x.y = fmaf(c.dt, v.y, x.y);
+    x.z = fmaf(c.dt, v.z, x.z);
+}
+
+__device__ __forceinline__ bool node_bad(float3 x, float3 v, float lim) {
+    // NaN fails every comparison, so test the good range and negate
+    const bool ok = fabsf(x.x) <= lim && fabsf(x.y) <= lim && fabsf(x.z) <= lim && fabsf(v.x) <= 3.0e38f &&
+                    fabsf(v.y) <= 3.0e38f && fabsf(v.z) <= 3.0e38f;
+    return !ok;
+}
+
+}  // namespace sr

@@ -1,0 +1,198 @@
+"""GPU parity of the build (voxels -> robot) and the time step against the
+FP64 oracle, through the C ABI.  Tolerances: positions within 1e-4 relative
+after 1000 contact-free steps and 1e-3 after 200 steps with contact;
+topology and spring numbering bit-exact."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (DEV, gpu_population, gpu_states, need_gpu, oracle_robots, rel_err, say, split,
+                      voxel_population)
+from paper_2405_00698_amd import SR_NO_ACTUATION, SR_NO_GRAVITY, SR_NO_GROUND, SR_STEP_PERSISTENT, SR_STEP_PLAIN
+
+pytestmark = pytest.mark.gpu
+
+C1 = [4] * 8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _springs_match(P, robots):
+    M, S, mo, so = P.counts()
+    sp = {k: v.cpu().numpy() for k, v in P.springs().items()}
+    for r, R in enumerate(robots):
+        o = R.springs()
+        assert (M[r], S[r]) == (R.M, R.S)
+        sl = slice(so[r], so[r + 1])
+        assert np.array_equal(sp["ij"][sl], o["ij"])
+        np.testing.assert_allclose(sp["L0"][sl], o["L0"], rtol=1e-6)
+        np.testing.assert_allclose(sp["k"][sl], o["k"], rtol=2e-6)
+        np.testing.assert_allclose(sp["a"][sl], o["a"], rtol=1e-5, atol=1e-7)
+        np.testing.assert_allclose(sp["phi"][sl], o["phi"], atol=1e-6)
+
+
+def test_build_from_voxels_matches_oracle(orc):
+    sides = C1 + [1, 2, 3, 5, 7, 9, 10, 12]
+    cls, w = voxel_population(sides, 7, p_empty=0.35)
+    say("build parity", sides)
+    P = gpu_population(sides, cls, w)
+    robots = oracle_robots(orc, sides, cls, w)
+    kept = P.voxels()[0].cpu().numpy()
+    o = 0
+    for n, R in zip(sides, robots):
+        assert np.array_equal(kept[o:o + n ** 3], R.kept())
+        o += n ** 3
+    _springs_match(P, robots)
+    xs, vs, st = gpu_states(P)
+    assert st == 0
+    for r, R in enumerate(robots):
+        x, v, _, _ = R.state()
+        np.testing.assert_allclose(xs[r], x, atol=1e-7)
+        assert np.all(vs[r] == 0)
+
+
+@pytest.mark.parametrize("mode", [SR_STEP_PERSISTENT, SR_STEP_PLAIN])
+@pytest.mark.parametrize("flags,steps,tol", [(SR_NO_GROUND, 1000, 1e-4),
+                                             (SR_NO_GROUND | SR_NO_GRAVITY, 1000, 1e-4),
+                                             (0, 200, 1e-3)])
+def test_step_parity_c1(orc, mode, flags, steps, tol):
+    cls, w = voxel_population(C1, 11)
+    say("step parity mode", mode, "flags", flags, "steps", steps)
+    P = gpu_population(C1, cls, w, flags=flags)
+    P.set_step_config(mode)
+    robots = oracle_robots(orc, C1, cls, w, flags=flags)
+    P.step(steps)
+    for R in robots:
+        R.step(steps)
+    xs, vs, st = gpu_states(P)
+    assert st == steps
+    fit = P.fitness().cpu().numpy()
+    for r, R in enumerate(robots):
+        x, v, _, _ = R.state()
+        assert rel_err(xs[r], x) <= tol, (r, rel_err(xs[r], x))
+        scale = max(np.abs(x).max(), 1e-30)
+        assert abs(fit[r] - R.fitness()) <= tol * scale
+
+
+def test_contact_parity_longer_horizon_reported(orc):
+    """Beyond the 200-step gate the FP32/FP64 gap with contact is measured, not bounded tightly."""
+    cls, w = voxel_population(C1, 12)
+    P = gpu_population(C1, cls, w)
+    robots = oracle_robots(orc, C1, cls, w)
+    P.step(1000)
+    for R in robots:
+        R.step(1000)
+    xs, _, _ = gpu_states(P)
+    errs = [rel_err(xs[r], R.state()[0]) for r, R in enumerate(robots)]
+    say("contact 1000-step relative errors", ["%.2e" % e for e in errs])
+    assert max(errs) < 1e-2
+
+
+def test_plain_and_persistent_agree_bitwise():
+    sides = [4] * 3 + [8] * 3 + [10] * 2
+    cls, w = voxel_population(sides, 13)
+    xs = []
+    for mode in (SR_STEP_PLAIN, SR_STEP_PERSISTENT):
+        P = gpu_population(sides, cls, w)
+        P.set_step_config(mode)
+        P.step(300)
+        x, v, _ = P.state()
+        xs.append((x.cpu().numpy(), v.cpu().numpy()))
+    assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
+
+
+@pytest.mark.parametrize("n,configs", [(8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5)]),
+                                       (10, [(448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
+                                             (448, 0), (448, 5), (704, 5), (1024, 5)]),
+                                       (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6)])])
+def test_persistent_variants_bitwise(n, configs):
+    sides = [n] * 4
+    cls, w = voxel_population(sides, 17)
+    ref = None
+    for bs, var in configs:
+        say("variant", n, bs, var)
+        P = gpu_population(sides, cls, w)
+        P.set_persist_variant(n, bs, var)
+        P.step(250)
+        x = P.state()[0].cpu().numpy()
+        if ref is None:
+            ref = x
+        else:
+            assert np.array_equal(x, ref), (bs, var)
+
+
+def test_split_run_and_state_roundtrip():
+    cls, w = voxel_population(C1, 19)
+    A = gpu_population(C1, cls, w)
+    A.step(600)
+    B = gpu_population(C1, cls, w)
+    B.step(250)
+    x, v, st = B.state()
+    C2 = gpu_population(C1, cls, w)
+    C2.set_state(x.clone(), v.clone(), st)
+    B.step(350)
+    C2.step(350)
+    xa, va, _ = A.state()
+    for P in (B, C2):
+        xb, vb, sb = P.state()
+        assert sb == 600
+        assert torch.equal(xa, xb) and torch.equal(va, vb)
+    assert torch.equal(A.fitness(), C2.fitness())
+
+
+def test_rest_lattice_static_and_fitness_zero():
+    cls, w = voxel_population(C1, 23)
+    P = gpu_population(C1, cls, w, flags=SR_NO_GRAVITY | SR_NO_GROUND | SR_NO_ACTUATION)
+    x0 = P.state()[0].clone()
+    P.step(500)
+    assert (P.state()[0] - x0).abs().max().item() < 1e-6
+    assert P.fitness().abs().max().item() < 1e-6
+
+
+def test_divergence_is_flagged_and_isolated(orc):
+    cls, w = voxel_population(C1, 29)
+    P = gpu_population(C1, cls, w)
+    M, S, mo, so = P.counts()
+    k = P.springs()["k"]
+    k[so[2]:so[3]] = 1e12
+    P.set_spring_params(k=k)
+    P.step(300)
+    st = P.status().cpu().numpy()
+    fit = P.fitness().cpu().numpy()
+    assert st.tolist() == [0, 0, 1, 0, 0, 0, 0, 0]
+    assert fit[2] == -math.inf and np.all(np.isfinite(np.delete(fit, 2)))
+
+
+def test_uneven_sizes_parity(orc):
+    sides = list(range(1, 13))
+    cls, w = voxel_population(sides, 31)
+    P = gpu_population(sides, cls, w)
+    robots = oracle_robots(orc, sides, cls, w)
+    P.step(150)
+    for R in robots:
+        R.step(150)
+    xs, _, _ = gpu_states(P)
+    for r, R in enumerate(robots):
+        assert rel_err(xs[r], R.state()[0]) <= 1e-3, sides[r]
+
+
+@pytest.mark.parametrize("R,n", [(256, 8), (4096, 10)])
+def test_full_size_sampled_parity(orc, R, n):
+    """Workload sizes (256 x 8^3 and 4096 x 10^3) in the benchmark's launch
+    configuration; a sample of robots is checked against the oracle."""
+    sides = [n] * R
+    cls, w = voxel_population(sides, 37)
+    say("full size", R, n)
+    P = gpu_population(sides, cls, w)
+    P.step(200)
+    xs, _, _ = gpu_states(P)
+    for r in (0, 1, R // 2, R - 1):
+        nv = n ** 3
+        Rb = orc.Robot(n, cls[r * nv:(r + 1) * nv], w[r * nv:(r + 1) * nv].astype(np.float64))
+        Rb.step(200)
+        assert rel_err(xs[r], Rb.state()[0]) <= 1e-3, r

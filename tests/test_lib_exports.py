@@ -1,0 +1,71 @@
+"""CPU checks of the C ABI: the HIP library loads and exports every entry
+point that include/*.h declares, and the ctypes mirrors of the parameter
+structs match the C layout (no device call is made)."""
+import ctypes as C
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names += re.findall(r"^\s*(?:int|const char\s*\*)\s*(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("pop_create", "pop_destroy", "pop_build_from_genomes", "pop_build_from_voxels", "pop_step",
+                 "pop_fitness", "ga_generation", "pop_backward"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2405_00698_amd import _lib
+    L = _lib.load()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_c(tmp_path):
+    from paper_2405_00698_amd import _lib
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "softrobot.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(sr_sim_params), sizeof(sr_ga_params),'
+                   ' offsetof(sr_sim_params, flags), offsetof(sr_ga_params, p_mut_thr), offsetof(sr_ga_params, mut_sigma));'
+                   ' return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = [int(t) for t in subprocess.check_output([str(exe)]).split()]
+    assert out == [C.sizeof(_lib.SimParams), C.sizeof(_lib.GAParams), _lib.SimParams.flags.offset,
+                   _lib.GAParams.p_mut_thr.offset, _lib.GAParams.mut_sigma.offset]
+
+
+def test_defaults_and_errors_without_device():
+    from paper_2405_00698_amd import _lib
+    L = _lib.load()
+    p = _lib.default_params()
+    assert abs(p.dt - 1e-4) < 1e-18 and p.mass == pytest.approx(0.1) and p.k_ground == 1e5
+    assert list(p.k_class) == [0.0, 1e4, 1e4, 3e3, 3e4]
+    # argument validation happens before any device work
+    h = C.c_void_p()
+    sides = (C.c_int32 * 1)(13)
+    assert L.pop_create(C.byref(p), 1, sides, None, C.byref(h)) == _lib.SR_EINVAL
+    assert b"grid_side" in L.sr_last_error()
+    assert L.pop_step(None, 1) == _lib.SR_EINVAL
+
+
+def test_product_path_does_not_touch_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2405_00698_amd")
+    for f in glob.glob(os.path.join(pkg, "**", "*.*"), recursive=True):
+        if f.endswith((".py", ".hip", ".h", ".cpp")):
+            txt = open(f).read()
+            assert "import oracle" not in txt and "from oracle" not in txt and "oracle.c" not in txt, f
