@@ -152,6 +152,32 @@ int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t varia
  * 1e3 n voxel lengths at the end of a launch is flagged diverged and frozen. */
 int pop_step(sr_pop *pop, int32_t n_steps);
 
+/* Puts every robot back at its build state (step 0, lattice positions, zero
+ * velocity, no divergence flag), keeping the spring parameters; restarts a
+ * recording that pop_record turned on. */
+int pop_reset(sr_pop *pop);
+
+/* Turns on checkpointing for the adjoint: the state is saved every
+ * checkpoint_every steps of the run that starts at the build (call right
+ * after the build, before pop_step), up to max_steps steps; 0 turns it off.
+ * Another build restarts the recording; pop_set_state, and new spring
+ * parameters after the first step, end it. */
+int pop_record(sr_pop *pop, int32_t checkpoint_every, int32_t max_steps);
+
+/* Reverse-mode gradient of J = sum_r dJ_dfitness[r] * fitness_r for the steps
+ * recorded since the build (dev [n_robots] float), by segments: each
+ * checkpointed segment is recomputed storing its states, then reversed
+ * step by step (contact and friction branches as taken).  Outputs (dev,
+ * canonical spring order, NULL to skip): dJ/dk, dJ/da, dJ/dphi per spring.
+ * g_genome (dev [n_robots][SR_GENOME_LEN] or NULL): dJ/dgenome through the
+ * sigmoid weight head, the parallel-sum rule and the MLP in FP32 (the class
+ * head, the component step and the topology carry no gradient); needs the
+ * genomes and B (dev) of the build and every class phase zero, else
+ * SR_EUNSUPPORTED.  SR_ESTATE without a recorded run.  Gradients of a
+ * diverged robot are undefined. */
+int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, float *g_phi,
+                 const float *genomes, const float *B, float *g_genome);
+
 /* fitness (dev, [n_robots] float): mean over nodes of x_x(now) - x_x(build),
  * i.e. the centre-of-mass displacement along +x; -inf for a diverged robot. */
 int pop_fitness(sr_pop *pop, float *fitness);

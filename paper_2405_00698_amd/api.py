@@ -85,6 +85,32 @@ class Population:
         check(_lib.load().pop_fitness(self.h, _ptr(out, torch.float32, self.R, "fitness")))
         return out
 
+    def reset(self):
+        check(_lib.load().pop_reset(self.h))
+
+    # ---------------------------------------------------------------- adjoint
+    def record(self, checkpoint_every, max_steps):
+        check(_lib.load().pop_record(self.h, int(checkpoint_every), int(max_steps)))
+
+    def backward(self, dJ_dfitness, genomes=None, B=None, springs=True):
+        """Gradients of sum_r dJ_dfitness[r] fitness_r over the recorded run."""
+        S = self.counts()[3][-1]
+        dev = self.device
+        out = {}
+        if springs:
+            for key in ("k", "a", "phi"):
+                out[key] = torch.empty(S, dtype=torch.float32, device=dev)
+        g_gen = None
+        if genomes is not None:
+            g_gen = torch.empty((self.R, _lib.GENOME_LEN), dtype=torch.float32, device=dev)
+            out["genome"] = g_gen
+        check(_lib.load().pop_backward(self.h, _ptr(dJ_dfitness, torch.float32, self.R, "dJ_dfitness"),
+                                       _ptr(out.get("k"), torch.float32), _ptr(out.get("a"), torch.float32),
+                                       _ptr(out.get("phi"), torch.float32),
+                                       _ptr(genomes, torch.float32, self.R * _lib.GENOME_LEN, "genomes"),
+                                       _ptr(B, torch.float32, 96, "B"), _ptr(g_gen, torch.float32)))
+        return out
+
     # ---------------------------------------------------------------- introspection
     def counts(self):
         if self._counts is None:
@@ -176,3 +202,47 @@ def ga_generation(fitness, genomes_in, genomes_out, cfg=None, seed=3, generation
                                     C.byref(cfg.params), int(seed), int(generation),
                                     _ptr(decisions, torch.int32, 3 * P, "decisions"), _stream_handle(stream)))
     return genomes_out
+
+
+class SpringFitness(torch.autograd.Function):
+    """fitness = F(k, a, phi): per-spring stiffness, amplitude and phase (canonical
+    order) of a built population, n_steps from the build state; the backward runs
+    the checkpointed adjoint (pop_backward)."""
+
+    @staticmethod
+    def forward(ctx, k, a, phi, pop, n_steps, checkpoint_every):
+        pop.reset()
+        pop.set_spring_params(k.detach().contiguous(), a.detach().contiguous(), phi.detach().contiguous())
+        pop.record(checkpoint_every, n_steps)
+        pop.step(n_steps)
+        ctx.pop = pop
+        return pop.fitness()
+
+    @staticmethod
+    def backward(ctx, gfit):
+        g = ctx.pop.backward(gfit.detach().float().contiguous())
+        return g["k"], g["a"], g["phi"], None, None, None
+
+
+class GenomeFitness(torch.autograd.Function):
+    """fitness = F(genomes): FP32 genome query and build, n_steps of simulation;
+    the backward runs the adjoint through the sigmoid weight head, the
+    parallel-sum rule and the MLP."""
+
+    @staticmethod
+    def forward(ctx, genomes, B, pop, n_steps, checkpoint_every):
+        g = genomes.detach().contiguous()
+        Bc = B.detach().contiguous()
+        pop.build_from_genomes(g, Bc, _lib.SR_QUERY_FP32)
+        pop.record(checkpoint_every, n_steps)
+        pop.reset()
+        pop.step(n_steps)
+        ctx.pop = pop
+        ctx.save_for_backward(g, Bc)
+        return pop.fitness()
+
+    @staticmethod
+    def backward(ctx, gfit):
+        g, Bc = ctx.saved_tensors
+        out = ctx.pop.backward(gfit.detach().float().contiguous(), genomes=g, B=Bc, springs=False)
+        return out["genome"], None, None, None, None

@@ -1,0 +1,552 @@
+// adjoint.hip -- reverse-mode gradient of J = sum_r g_r fitness_r through the
+// time steps, the spring parameters, the parallel-sum rule and the genome MLP.
+//
+// Forward step n (all nodes, positions x_n): F = springs(x_n, t_n) + gravity +
+// ground(z_n); v' = v_n + dt F / m; v'' = friction(v', z_n); v_{n+1} = damping v'';
+// x_{n+1} = x_n + dt v_{n+1}.  Its reverse, for adjoints (lx, lv) of (x_{n+1}, v_{n+1}):
+//   lvt = damping (lv + dt lx);  lv' = friction Jacobian^T lvt (and a z term);
+//   lF = dt/m lv';  lv_n = lv';  lx_n = lx + ground/friction z terms + sum over
+//   springs of K_s (lF_hi - lF_lo) (to the lower end, minus to the upper end),
+// with K_s = k [(1 - L/r)(I - d^ d^T) + d^ d^T] the spring Hessian.  Per spring
+// dJ/dk += -(r - L) d^.(lF_hi - lF_lo) and dJ/dL = k d^.(lF_hi - lF_lo), split by
+// L = L0 + L0 a (sin(w t) cos phi + cos(w t) sin phi) into sums GS, GC of
+// dJ/dL times sin(w t_n) and cos(w t_n).  Contact and friction branches are those
+// the forward run took (the recorded states decide them).
+#include <cmath>
+
+#include "spring.h"
+
+namespace sr {
+
+namespace {
+
+struct AArgs {
+    const RobotInfo *robots;
+    const int32_t *list;
+    int count;
+    Planes pl;
+    const float4 *x0;
+    const float4 *rec_x, *rec_v;  // [n_steps * slot_base + t * slots + s]
+    int n_steps;
+    const float2 *sc;
+    float4 *lx, *lv;    // per slot
+    float *gk, *gs, *gc;  // per stencil entry
+    SimConst c;
+};
+
+template <int N, int BS, bool PHASE>
+__global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
+    using G = Geo<N>;
+    constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL;
+    constexpr int NPT = (SL + BS - 1) / BS;
+    __shared__ float4 xs[2][XL];
+    __shared__ float4 lf[2][XL];
+    const int tid = threadIdx.x;
+    const SimConst c = A.c;
+    const bool ground = c.ground != 0;
+    const float fz = c.mu_kc_dt_m;  // d(dv)/d(-z) = mu kc dt / m
+
+    for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
+        const int r = A.list[q];
+        const int base = A.robots[r].slot_base;
+        const int pbase = NDIR * base;
+        const size_t rbase = (size_t)A.n_steps * base;
+        const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f), zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = tid; i < PAD; i += BS) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                xs[b][i] = ghost;
+                xs[b][PAD + SL + i] = ghost;
+                lf[b][i] = zero;
+                lf[b][PAD + SL + i] = zero;
+            }
+        }
+
+        bool pres[NPT];
+        float3 X0[NPT], lx[NPT], lv[NPT];
+        float pk[NPT][NDIR], pa[NPT][NDIR], pb[NPT][NDIR], pik[NPT][NDIR];
+        float qk[NPT][NDIR], qa[NPT][NDIR], qb[NPT][NDIR];
+        float gk[NPT][NDIR], gs[NPT][NDIR], gc[NPT][NDIR];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            const bool live = s < SL;
+            const int sc_ = live ? s : 0;
+            const float4 P0 = A.x0[base + sc_];
+            pres[k] = live && P0.w != 0.f;
+            X0[k] = make_float3(P0.x, P0.y, P0.z);
+            const float4 LX = A.lx[base + sc_], LV = A.lv[base + sc_];
+            lx[k] = make_float3(LX.x, LX.y, LX.z);
+            lv[k] = make_float3(LV.x, LV.y, LV.z);
+#pragma unroll
+            for (int d = 0; d < NDIR; ++d) {
+                const int pi = pbase + d * SL + sc_;
+                const float kk = live ? A.pl.k[pi] : 0.f;
+                pk[k][d] = kk;
+                pa[k][d] = live ? A.pl.kal[pi] : 0.f;
+                pb[k][d] = (live && PHASE) ? A.pl.kbe[pi] : 0.f;
+                pik[k][d] = kk != 0.f ? 1.0f / kk : 0.f;
+                gk[k][d] = live ? A.gk[pi] : 0.f;
+                gs[k][d] = live ? A.gs[pi] : 0.f;
+                gc[k][d] = live ? A.gc[pi] : 0.f;
+                const int lo = s - dir_off(d, N);
+                const bool ok = live && lo >= 0;
+                const int qi = pbase + d * SL + (ok ? lo : 0);
+                qk[k][d] = ok ? A.pl.k[qi] : 0.f;
+                qa[k][d] = ok ? A.pl.kal[qi] : 0.f;
+                qb[k][d] = (ok && PHASE) ? A.pl.kbe[qi] : 0.f;
+            }
+        }
+        __syncthreads();
+
+        for (int t = A.n_steps - 1; t >= 0; --t) {
+            const int b = t & 1;
+            const float2 sct = A.sc[t];
+            float3 Xr[NPT], LF[NPT];
+            // node-local part of the reverse step
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int s = tid + k * BS;
+                if (s >= SL) continue;
+                float3 X = X0[k], lF = make_float3(0.f, 0.f, 0.f);
+                if (pres[k]) {
+                    const float4 XR = A.rec_x[rbase + (size_t)t * SL + s];
+                    const float4 VP = A.rec_v[rbase + (size_t)t * SL + s];
+                    X = make_float3(XR.x, XR.y, XR.z);
+                    float ux = c.damping * fmaf(c.dt, lx[k].x, lv[k].x);
+                    float uy = c.damping * fmaf(c.dt, lx[k].y, lv[k].y);
+                    const float uz = c.damping * fmaf(c.dt, lx[k].z, lv[k].z);
+                    const bool below = ground && X.z < 0.f;
+                    if (below) {
+                        const float dv = c.mu_kc_dt_m * (-X.z);
+                        const float u = sqrtf(fmaf(VP.y, VP.y, VP.x * VP.x));
+                        if (u <= dv) {
+                            ux = 0.f;
+                            uy = 0.f;
+                        } else {
+                            const float hx = VP.x / u, hy = VP.y / u;
+                            const float dot = fmaf(hy, uy, hx * ux);
+                            lx[k].z = fmaf(fz, dot, lx[k].z);
+                            const float cc = dv / u;
+                            const float nx = ux - cc * (ux - hx * dot);
+                            const float ny = uy - cc * (uy - hy * dot);
+                            ux = nx;
+                            uy = ny;
+                        }
+                    }
+                    lv[k] = make_float3(ux, uy, uz);
+                    lF = make_float3(c.dt_m * ux, c.dt_m * uy, c.dt_m * uz);
+                    if (below) lx[k].z = fmaf(-c.kc, lF.z, lx[k].z);
+                }
+                Xr[k] = X;
+                LF[k] = lF;
+                xs[b][PAD + s] = make_float4(X.x, X.y, X.z, 0.f);
+                lf[b][PAD + s] = make_float4(lF.x, lF.y, lF.z, 0.f);
+            }
+            __syncthreads();
+            // spring part: every node takes K_s (lF_hi - lF_lo) from each spring it touches
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int s = tid + k * BS;
+                if (s >= SL || !pres[k]) continue;
+                const float4 *xsb = xs[b] + s;
+                const float4 *lfb = lf[b] + s;
+                float3 acc = make_float3(0.f, 0.f, 0.f);
+#pragma unroll
+                for (int d = 0; d < NDIR; ++d) {
+                    // forward spring: self is the lower end
+                    const float3 Y = ld3(xsb + (PAD + dir_off(d, N)));
+                    const float3 LJ = ld3(lfb + (PAD + dir_off(d, N)));
+                    const float dx = Y.x - Xr[k].x, dy = Y.y - Xr[k].y, dz = Y.z - Xr[k].z;
+                    const float ux = LJ.x - LF[k].x, uy = LJ.y - LF[k].y, uz = LJ.z - LF[k].z;
+                    const float r2 = len2(dx, dy, dz);
+                    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+                    float kL = fmaf(pa[k][d], sct.x, pk[k][d] * L0d(c, d));
+                    if (PHASE) kL = fmaf(pb[k][d], sct.y, kL);
+                    const float c1 = fmaf(-kL, ir, pk[k][d]);
+                    const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+                    const float c2 = (kL * ir) * ir * ir * du;
+                    acc.x += fmaf(c1, ux, c2 * dx);
+                    acc.y += fmaf(c1, uy, c2 * dy);
+                    acc.z += fmaf(c1, uz, c2 * dz);
+                    const float dhu = du * ir;
+                    gk[k][d] = fmaf(-(r2 * ir - kL * pik[k][d]), dhu, gk[k][d]);
+                    const float gL = pk[k][d] * dhu;
+                    gs[k][d] = fmaf(gL, sct.x, gs[k][d]);
+                    gc[k][d] = fmaf(gL, sct.y, gc[k][d]);
+                }
+#pragma unroll
+                for (int d = 0; d < NDIR; ++d) {
+                    // backward spring: self is the upper end
+                    const float3 Y = ld3(xsb + (PAD - dir_off(d, N)));
+                    const float3 LI = ld3(lfb + (PAD - dir_off(d, N)));
+                    const float dx = Xr[k].x - Y.x, dy = Xr[k].y - Y.y, dz = Xr[k].z - Y.z;
+                    const float ux = LF[k].x - LI.x, uy = LF[k].y - LI.y, uz = LF[k].z - LI.z;
+                    const float r2 = len2(dx, dy, dz);
+                    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+                    float kL = fmaf(qa[k][d], sct.x, qk[k][d] * L0d(c, d));
+                    if (PHASE) kL = fmaf(qb[k][d], sct.y, kL);
+                    const float c1 = fmaf(-kL, ir, qk[k][d]);
+                    const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+                    const float c2 = (kL * ir) * ir * ir * du;
+                    acc.x -= fmaf(c1, ux, c2 * dx);
+                    acc.y -= fmaf(c1, uy, c2 * dy);
+                    acc.z -= fmaf(c1, uz, c2 * dz);
+                }
+                lx[k].x += acc.x;
+                lx[k].y += acc.y;
+                lx[k].z += acc.z;
+            }
+        }
+        // the adjoint state and the gradient sums carry over to the previous segment
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            if (s >= SL) continue;
+            A.lx[base + s] = make_float4(lx[k].x, lx[k].y, lx[k].z, 0.f);
+            A.lv[base + s] = make_float4(lv[k].x, lv[k].y, lv[k].z, 0.f);
+#pragma unroll
+            for (int d = 0; d < NDIR; ++d) {
+                const int pi = pbase + d * SL + s;
+                A.gk[pi] = gk[k][d];
+                A.gs[pi] = gs[k][d];
+                A.gc[pi] = gc[k][d];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Terminal adjoint of J = sum_r g_r (1/M_r) sum_i (x_i,x - x0_i,x): lx = g_r / M_r e_x on
+// present nodes, lv = 0, gradient sums zero.
+__global__ void k_adj_init(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const float4 *x0,
+                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_slots) return;
+    const int r = slot_robot[g];
+    const RobotInfo ri = robots[r];
+    const bool pres = x0[g].w != 0.f;
+    const float val = (pres && ri.M > 0) ? dJ[r] / (float)ri.M : 0.f;
+    lx[g] = make_float4(val, 0.f, 0.f, 0.f);
+    lv[g] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int s = g - ri.slot_base;
+    for (int d = 0; d < NDIR; ++d) {
+        const int pi = NDIR * ri.slot_base + d * ri.slots + s;
+        gk[pi] = 0.f;
+        gs[pi] = 0.f;
+        gc[pi] = 0.f;
+    }
+}
+
+// Per spring: dJ/dk, dJ/da, dJ/dphi in canonical order, from the stencil sums.
+__global__ void k_adj_springs(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const int32_t *sid,
+                              const int64_t *spring_off, Planes pl, float voxel_len, const float *gk, const float *gs,
+                              const float *gc, float *g_k, float *g_a, float *g_phi) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_slots) return;
+    const int r = slot_robot[g];
+    const RobotInfo ri = robots[r];
+    const int s = g - ri.slot_base;
+    for (int d = 0; d < NDIR; ++d) {
+        const int pi = NDIR * ri.slot_base + d * ri.slots + s;
+        const int id = sid[pi];
+        if (id < 0) continue;
+        const int64_t o = spring_off[r] + id;
+        const float L0 = voxel_len * sqrtf((float)dir_len2(d));
+        const float kL0 = pl.kL0[pi], kal = pl.kal[pi], kbe = pl.kbe[pi];
+        float a = 0.f, cph = 1.f, sph = 0.f;
+        if (kL0 != 0.f) {
+            if (kbe == 0.f) a = kal / kL0;
+            else {
+                a = sqrtf(kal * kal + kbe * kbe) / kL0;
+                const float ph = atan2f(kbe, kal);
+                cph = cosf(ph);
+                sph = sinf(ph);
+            }
+        }
+        if (g_k) g_k[o] = gk[pi];
+        if (g_a) g_a[o] = L0 * (gs[pi] * cph + gc[pi] * sph);
+        if (g_phi) g_phi[o] = L0 * a * (gc[pi] * cph - gs[pi] * sph);
+    }
+}
+
+// dJ/dw per voxel through the parallel-sum rule (all class phases zero):
+// dk_s/dw_v = k_c(v), da_s/dw_v = k_c(v) (a_c(v) - a_s) / k_s, summed over the
+// 28 springs of the kept voxel.
+struct DwArgs {
+    const RobotInfo *robots;
+    int total_vox;
+    const int32_t *vox_robot;
+    const uint8_t *kept;
+    Planes pl;
+    const float *gk, *gs;
+    float k_class[5], a_class[5];
+    float voxel_len;
+    float *dJdw;
+};
+
+__global__ void k_adj_dw(DwArgs A) {
+    const int gv = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gv >= A.total_vox) return;
+    const int r = A.vox_robot[gv];
+    const RobotInfo ri = A.robots[r];
+    const int v = gv - ri.vox_base;
+    const int c = A.kept[gv];
+    if (c == 0) {
+        A.dJdw[gv] = 0.f;
+        return;
+    }
+    const int n = ri.n, N = ri.N;
+    const int i = v % n, j = (v / n) % n, kk = v / (n * n);
+    const float kc = A.k_class[c], ac = A.a_class[c];
+    float sum = 0.f;
+    for (int c1 = 0; c1 < 8; ++c1) {
+        const int a1 = i + (c1 & 1), b1 = j + ((c1 >> 1) & 1), z1 = kk + (c1 >> 2);
+        const int l1 = a1 + N * (b1 + N * z1);
+        for (int c2 = 0; c2 < 8; ++c2) {
+            const int a2 = i + (c2 & 1), b2 = j + ((c2 >> 1) & 1), z2 = kk + (c2 >> 2);
+            const int l2 = a2 + N * (b2 + N * z2);
+            if (l2 <= l1) continue;
+            // forward direction from corner 1 to corner 2
+            const int dx = a2 - a1, dy = b2 - b1, dz = z2 - z1;
+            int d = -1;
+            for (int q = 0; q < NDIR; ++q)
+                if (dir_dx(q) == dx && dir_dy(q) == dy && dir_dz(q) == dz) d = q;
+            const int pi = NDIR * ri.slot_base + d * ri.slots + l1;
+            const float ks = A.pl.k[pi];
+            const float L0 = A.voxel_len * sqrtf((float)dir_len2(d));
+            const float as = A.pl.kL0[pi] != 0.f ? A.pl.kal[pi] / A.pl.kL0[pi] : 0.f;
+            const float ga = L0 * A.gs[pi];
+            float t = A.gk[pi];
+            if (ks != 0.f) t += (ac - as) / ks * ga;
+            sum += kc * t;
+        }
+    }
+    A.dJdw[gv] = sum;
+}
+
+// Genome gradient: for each voxel with dJ/dw != 0, recompute the FP32 forward
+// (encoding, two tanh layers, sigmoid head), g5 = dJ/dw w (1 - w), then back
+// through W3 row 5, W2 and W1.  One workgroup per robot; weight gradients are
+// accumulated in registers over tiles of 64 voxels staged in LDS.
+constexpr int OFF_W1 = 0, OFF_B1 = 4096, OFF_W2 = 4160, OFF_B2 = 8256, OFF_W3 = 8320, OFF_B3 = 8704;
+
+__global__ __launch_bounds__(256) void k_mlp_backward(const RobotInfo *robots, const float *genomes, const float *B,
+                                                      const float *dJdw, float *g_gen) {
+    __shared__ float W1[64 * 64], W2[64 * 64], w3[64], b1[64], b2[64];
+    __shared__ float Bs[96];
+    __shared__ float gam[64][65], h1[64][65], h2[64][65], d2[64][65], d1[64][65];
+    __shared__ float gv5[64];
+    __shared__ float b3s;
+    const int r = blockIdx.x;
+    const RobotInfo ri = robots[r];
+    const int n = ri.n, nv = n * n * n;
+    const float *g = genomes + (size_t)r * SR_GENOME_LEN;
+    float *out = g_gen + (size_t)r * SR_GENOME_LEN;
+    const int tid = threadIdx.x;
+    for (int q = tid; q < 4096; q += 256) {
+        W1[q] = g[OFF_W1 + q];
+        W2[q] = g[OFF_W2 + q];
+    }
+    if (tid < 64) {
+        w3[tid] = g[OFF_W3 + 5 * 64 + tid];
+        b1[tid] = g[OFF_B1 + tid];
+        b2[tid] = g[OFF_B2 + tid];
+    }
+    if (tid < 96) Bs[tid] = B[tid];
+    if (tid == 0) b3s = g[OFF_B3 + 5];
+    __syncthreads();
+    // accumulators: thread owns W1/W2 gradient entries e = tid + 256 m, m < 16
+    float aW1[16], aW2[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        aW1[m] = 0.f;
+        aW2[m] = 0.f;
+    }
+    float aB1 = 0.f, aB2 = 0.f, aW3 = 0.f, aB3 = 0.f;
+    const float inv = 1.0f / (float)n;
+    for (int v0 = 0; v0 < nv; v0 += 64) {
+        // forward for voxel v0 + lane of wave 0..3: each thread does a quarter of one voxel's work
+        const int vl = tid & 63, part = tid >> 6;
+        const int vid = v0 + vl;
+        const bool act = vid < nv && dJdw[ri.vox_base + vid] != 0.f;
+        {
+            const float vx = (((vid % n)) + 0.5f) * inv, vy = (((vid / n) % n) + 0.5f) * inv, vz = ((vid / (n * n)) + 0.5f) * inv;
+            for (int q = part * 8; q < part * 8 + 8; ++q) {
+                const float t = 2.0f * fmaf(Bs[3 * q + 2], vz, fmaf(Bs[3 * q + 1], vy, Bs[3 * q] * vx));
+                float sn, cs;
+                sincospif(t, &sn, &cs);
+                gam[vl][q] = act ? cs : 0.f;
+                gam[vl][32 + q] = act ? sn : 0.f;
+            }
+        }
+        __syncthreads();
+        for (int o = part * 16; o < part * 16 + 16; ++o) {
+            float a = b1[o];
+#pragma unroll 8
+            for (int jj = 0; jj < 64; ++jj) a = fmaf(W1[o * 64 + jj], gam[vl][jj], a);
+            h1[vl][o] = act ? tanhf(a) : 0.f;
+        }
+        __syncthreads();
+        for (int o = part * 16; o < part * 16 + 16; ++o) {
+            float a = b2[o];
+#pragma unroll 8
+            for (int jj = 0; jj < 64; ++jj) a = fmaf(W2[o * 64 + jj], h1[vl][jj], a);
+            h2[vl][o] = act ? tanhf(a) : 0.f;
+        }
+        __syncthreads();
+        if (part == 0) {
+            float o5 = b3s;
+            for (int jj = 0; jj < 64; ++jj) o5 = fmaf(w3[jj], h2[vl][jj], o5);
+            const float w = 1.0f / (1.0f + expf(-o5));
+            gv5[vl] = act ? dJdw[ri.vox_base + vid] * w * (1.0f - w) : 0.f;
+        }
+        __syncthreads();
+        // W3 row 5 and b3[5] gradients (threads 0..63 own one entry each of W3 row 5)
+        if (tid < 64) {
+            float sacc = 0.f;
+            for (int vv = 0; vv < 64; ++vv) sacc = fmaf(gv5[vv], h2[vv][tid], sacc);
+            aW3 += sacc;
+        }
+        if (tid == 64) {
+            float sacc = 0.f;
+            for (int vv = 0; vv < 64; ++vv) sacc += gv5[vv];
+            aB3 += sacc;
+        }
+        __syncthreads();
+        // d2 = g5 w3 (1 - h2^2)
+        for (int o = part * 16; o < part * 16 + 16; ++o) {
+            const float hh = h2[vl][o];
+            d2[vl][o] = gv5[vl] * w3[o] * (1.0f - hh * hh);
+        }
+        __syncthreads();
+        // d1 = (W2^T d2) (1 - h1^2)
+        for (int o = part * 16; o < part * 16 + 16; ++o) {
+            float a = 0.f;
+#pragma unroll 8
+            for (int ii = 0; ii < 64; ++ii) a = fmaf(W2[ii * 64 + o], d2[vl][ii], a);
+            const float hh = h1[vl][o];
+            d1[vl][o] = a * (1.0f - hh * hh);
+        }
+        __syncthreads();
+        // outer products over the tile's voxels; entry e = tid + 256 m is row
+        // (tid >> 6) + 4 m, column tid & 63 of W1 / W2
+        {
+            const int ij = tid & 63, oi0 = tid >> 6;
+#pragma unroll 2
+            for (int vv = 0; vv < 64; ++vv) {
+                const float gj = gam[vv][ij], hj = h1[vv][ij];
+#pragma unroll
+                for (int m = 0; m < 16; ++m) {
+                    aW1[m] = fmaf(d1[vv][oi0 + 4 * m], gj, aW1[m]);
+                    aW2[m] = fmaf(d2[vv][oi0 + 4 * m], hj, aW2[m]);
+                }
+            }
+        }
+        if (tid < 64) {
+            float s1 = 0.f, s2 = 0.f;
+            for (int vv = 0; vv < 64; ++vv) {
+                s1 += d1[vv][tid];
+                s2 += d2[vv][tid];
+            }
+            aB1 += s1;
+            aB2 += s2;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int e = tid + 256 * m;
+        out[OFF_W1 + e] = aW1[m];
+        out[OFF_W2 + e] = aW2[m];
+    }
+    if (tid < 64) {
+        out[OFF_B1 + tid] = aB1;
+        out[OFF_B2 + tid] = aB2;
+        for (int row = 0; row < 6; ++row) out[OFF_W3 + row * 64 + tid] = row == 5 ? aW3 : 0.f;
+    }
+    if (tid < 5) out[OFF_B3 + tid] = 0.f;  // class logits carry no gradient
+    if (tid == 64) out[OFF_B3 + 5] = aB3;
+}
+
+typedef void (*AdjFn)(AArgs);
+struct AdjEntry {
+    int n, block;
+    AdjFn fn, fn_phase;
+};
+#define SR_AE(NN, BS) \
+    { NN, BS, k_adjoint<NN + 1, BS, false>, k_adjoint<NN + 1, BS, true> }
+const AdjEntry kAdj[] = {SR_AE(1, 64),   SR_AE(2, 64),   SR_AE(3, 64),    SR_AE(4, 128),
+                         SR_AE(5, 256),  SR_AE(6, 384),  SR_AE(7, 512),   SR_AE(8, 768),
+                         SR_AE(9, 1024), SR_AE(10, 704), SR_AE(11, 1024)};
+
+}  // namespace
+
+hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
+                          const float4 *x0, const float4 *rec_x, const float4 *rec_v, int n_steps, const float2 *sc,
+                          float4 *lx, float4 *lv, float *gk, float *gs, float *gc, SimConst c, hipStream_t st) {
+    const AdjEntry *e = nullptr;
+    for (const auto &q : kAdj)
+        if (q.n == n) e = &q;
+    if (!e) return hipErrorInvalidConfiguration;
+    AArgs A;
+    A.robots = robots;
+    A.list = list;
+    A.count = count;
+    A.pl = pl;
+    A.x0 = x0;
+    A.rec_x = rec_x;
+    A.rec_v = rec_v;
+    A.n_steps = n_steps;
+    A.sc = sc;
+    A.lx = lx;
+    A.lv = lv;
+    A.gk = gk;
+    A.gs = gs;
+    A.gc = gc;
+    A.c = c;
+    hipLaunchKernelGGL(phase ? e->fn_phase : e->fn, dim3(count), dim3(e->block), 0, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_init(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const float4 *x0,
+                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_init, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots, slot_robot,
+                       x0, dJ, lx, lv, gk, gs, gc);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_springs(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const int32_t *sid,
+                              const int64_t *spring_off, Planes pl, float voxel_len, const float *gk, const float *gs,
+                              const float *gc, float *g_k, float *g_a, float *g_phi, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_springs, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots,
+                       slot_robot, sid, spring_off, pl, voxel_len, gk, gs, gc, g_k, g_a, g_phi);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_genome(const RobotInfo *robots, int R, int total_vox, const int32_t *vox_robot,
+                             const uint8_t *kept, Planes pl, const float *gk, const float *gs,
+                             const sr_sim_params &p, const float *genomes, const float *B, float *dJdw, float *g_gen,
+                             hipStream_t st) {
+    DwArgs A;
+    A.robots = robots;
+    A.total_vox = total_vox;
+    A.vox_robot = vox_robot;
+    A.kept = kept;
+    A.pl = pl;
+    A.gk = gk;
+    A.gs = gs;
+    for (int c = 0; c < 5; ++c) {
+        A.k_class[c] = p.k_class[c];
+        A.a_class[c] = p.a_class[c];
+    }
+    A.voxel_len = p.voxel_len;
+    A.dJdw = dJdw;
+    hipLaunchKernelGGL(k_adj_dw, dim3((total_vox + 255) / 256), dim3(256), 0, st, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_backward, dim3(R), dim3(256), 0, st, robots, genomes, B, dJdw, g_gen);
+    return hipGetLastError();
+}
+
+}  // namespace sr

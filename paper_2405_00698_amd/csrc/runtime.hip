@@ -64,6 +64,16 @@ struct sr_pop {
     // genome query scratch
     uint8_t *q_cls = nullptr;
     float *q_w = nullptr;
+    int32_t *vox_robot = nullptr;
+    // adjoint: checkpoints of (x, v) at steps 0, K, 2K, ... since the build
+    int ck_every = 0, ck_cap = 0;
+    bool rec_valid = false;
+    float4 *ck_x = nullptr, *ck_v = nullptr;
+    // adjoint scratch (grown on demand)
+    int rec_cap = 0;
+    float4 *rec_x = nullptr, *rec_v = nullptr, *tmp_x = nullptr, *tmp_v = nullptr, *lx = nullptr, *lv = nullptr;
+    float *gk = nullptr, *gs = nullptr, *gc = nullptr, *dJdw = nullptr;
+    float2 *sc_seg = nullptr;
 };
 
 namespace {
@@ -97,7 +107,9 @@ void pop_free(sr_pop *pop) {
                     pop->sid, pop->x0, pop->xbuf[0], pop->xbuf[1], pop->vbuf[0], pop->vbuf[1],
                     pop->slot_node, pop->node_slot, pop->slot_robot, pop->rows, pop->entries,
                     pop->bad_class, pop->diverged, pop->d_step, pop->sc, pop->d_lists, pop->d_mass_off,
-                    pop->d_spring_off, pop->q_cls, pop->q_w};
+                    pop->d_spring_off, pop->q_cls, pop->q_w, pop->vox_robot, pop->ck_x, pop->ck_v,
+                    pop->rec_x, pop->rec_v, pop->tmp_x, pop->tmp_v, pop->lx, pop->lv, pop->gk, pop->gs,
+                    pop->gc, pop->dJdw, pop->sc_seg};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -143,8 +155,7 @@ int finish_build(sr_pop *pop) {
     pop->h_step = 0;
     pop->h_step_stage = 0;
     HIPC(pop, hipMemcpyAsync(pop->d_step, &pop->h_step_stage, sizeof(int64_t), hipMemcpyHostToDevice, pop->st));
-    uint8_t bad_host[1] = {0};
-    (void)bad_host;
+    pop->rec_valid = pop->ck_every > 0;
     std::vector<uint8_t> bad(pop->R);
     HIPC(pop, hipMemcpyAsync(bad.data(), pop->bad_class, pop->R, hipMemcpyDeviceToHost, pop->st));
     HIPC(pop, hipStreamSynchronize(pop->st));
@@ -259,6 +270,7 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
     ALLOC(pop->d_spring_off, (size_t)n_robots + 1);
     ALLOC(pop->q_cls, (size_t)vox);
     ALLOC(pop->q_w, (size_t)vox);
+    ALLOC(pop->vox_robot, (size_t)vox);
 #undef ALLOC
     if (e != hipSuccess) {
         pop_free(pop);
@@ -268,6 +280,10 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
     std::vector<int32_t> slot_robot(S);
     for (int r = 0; r < n_robots; ++r)
         for (int s = 0; s < pop->h_robots[r].slots; ++s) slot_robot[pop->h_robots[r].slot_base + s] = r;
+    std::vector<int32_t> vox_robot((size_t)vox);
+    for (int r = 0; r < n_robots; ++r)
+        for (int q = 0; q < pop->h_robots[r].n * pop->h_robots[r].n * pop->h_robots[r].n; ++q)
+            vox_robot[pop->h_robots[r].vox_base + q] = r;
     std::vector<int32_t> lists;
     for (auto &kv : by_side) {
         SideGroup g;
@@ -284,6 +300,8 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
                        pop->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pop->slot_robot, slot_robot.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, pop->st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pop->vox_robot, vox_robot.data(), sizeof(int32_t) * vox, hipMemcpyHostToDevice, pop->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pop->d_lists, lists.data(), sizeof(int32_t) * n_robots, hipMemcpyHostToDevice, pop->st);
     if (e == hipSuccess) e = hipMemsetAsync(pop->bad_class, 0, n_robots, pop->st);
@@ -372,27 +390,47 @@ int pop_step(sr_pop *pop, int32_t n_steps) {
     if (rc) return rc;
     const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
     HIPC(pop, launch_sincos(pop->sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, pop->st));
-    if (pop->mode == SR_STEP_PLAIN) {
-        for (int t = 0; t < n_steps; ++t) {
-            const int a = pop->cur, b = 1 - pop->cur;
-            HIPC(pop, launch_plain_step(pop->d_robots, pop->R, pop->total_slots, pop->rows, pop->entries, pop->pl,
-                                        pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], pop->sc, t,
-                                        pop->phase, pop->diverged, pop->slot_robot, pop->c, pop->st));
-            pop->cur = b;
+    const int K = pop->rec_valid ? pop->ck_every : 0;
+    for (int t = 0; t < n_steps;) {
+        const int64_t g = pop->h_step + t;  // step index at the start of this block
+        int len = n_steps - t;
+        if (pop->spl > 0 && len > pop->spl) len = pop->spl;
+        if (K > 0 && pop->rec_valid) {
+            if (g % K == 0) {
+                const int64_t cidx = g / K;
+                if (cidx < pop->ck_cap) {
+                    const size_t off = (size_t)cidx * pop->total_slots;
+                    HIPC(pop, hipMemcpyAsync(pop->ck_x + off, pop->xbuf[pop->cur], sizeof(float4) * pop->total_slots,
+                                             hipMemcpyDeviceToDevice, pop->st));
+                    HIPC(pop, hipMemcpyAsync(pop->ck_v + off, pop->vbuf[pop->cur], sizeof(float4) * pop->total_slots,
+                                             hipMemcpyDeviceToDevice, pop->st));
+                } else {
+                    pop->rec_valid = false;  // past the recorded horizon
+                }
+            }
+            const int to_ck = (int)(K - g % K);
+            if (len > to_ck) len = to_ck;
         }
-        HIPC(pop, launch_check_div(pop->d_robots, pop->R, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->diverged,
-                                   pop->c.lim, pop->st));
-    } else {
-        const int spl = pop->spl > 0 ? pop->spl : n_steps;
-        for (int t0 = 0; t0 < n_steps; t0 += spl) {
-            const int cnt = (n_steps - t0) < spl ? (n_steps - t0) : spl;
-            for (const auto &g : pop->groups) {
-                HIPC(pop, launch_persistent(g.cfg, pop->phase, pop->d_robots, pop->d_lists + g.offset, g.count,
-                                            g.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->sc + t0,
-                                            cnt, pop->diverged, pop->c, pop->st));
+        if (pop->mode == SR_STEP_PLAIN) {
+            for (int q = 0; q < len; ++q) {
+                const int a = pop->cur, b = 1 - pop->cur;
+                HIPC(pop, launch_plain_step(pop->d_robots, pop->R, pop->total_slots, pop->rows, pop->entries, pop->pl,
+                                            pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], pop->sc, t + q,
+                                            pop->phase, pop->diverged, pop->slot_robot, pop->c, pop->st));
+                pop->cur = b;
+            }
+        } else {
+            for (const auto &gr : pop->groups) {
+                HIPC(pop, launch_persistent(gr.cfg, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count,
+                                            gr.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->sc + t,
+                                            len, pop->diverged, pop->c, pop->st));
             }
         }
+        t += len;
     }
+    if (pop->mode == SR_STEP_PLAIN)
+        HIPC(pop, launch_check_div(pop->d_robots, pop->R, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->diverged,
+                                   pop->c.lim, pop->st));
     HIPC(pop, launch_advance(pop->d_step, n_steps, pop->st));
     pop->h_step += n_steps;
     return SR_OK;
@@ -453,6 +491,7 @@ int pop_set_spring_params(sr_pop *pop, const float *k, const float *a, const flo
     int rc = ensure_counts(pop);
     if (rc) return rc;
     if (phi) pop->phase = true;
+    if (pop->h_step > 0) pop->rec_valid = false;  // the recorded run used other parameters
     HIPC(pop, launch_springs_io(pop->d_robots, pop->R, pop->total_slots, pop->slot_robot, pop->slot_node, pop->sid,
                                 pop->d_spring_off, pop->pl, pop->p.voxel_len, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, k, a, phi, 1, pop->st));
@@ -482,6 +521,7 @@ int pop_set_state(sr_pop *pop, const float *x, const float *v, int64_t step) {
     HIPC(pop, hipStreamSynchronize(pop->st));
     pop->h_step = step;
     pop->h_step_stage = step;
+    pop->rec_valid = false;
     HIPC(pop, hipMemcpyAsync(pop->d_step, &pop->h_step_stage, sizeof(int64_t), hipMemcpyHostToDevice, pop->st));
     HIPC(pop, hipMemsetAsync(pop->diverged, 0, pop->R, pop->st));
     HIPC(pop, hipStreamSynchronize(pop->st));
@@ -492,6 +532,125 @@ int pop_get_status(sr_pop *pop, uint8_t *diverged) {
     CHECK_POP(pop);
     if (!diverged) return set_err(SR_EINVAL, "null output");
     HIPC(pop, hipMemcpyAsync(diverged, pop->diverged, pop->R, hipMemcpyDeviceToDevice, pop->st));
+    return SR_OK;
+}
+
+int pop_reset(sr_pop *pop) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_reset before a build");
+    HIPC(pop, hipMemcpyAsync(pop->xbuf[0], pop->x0, sizeof(float4) * pop->total_slots, hipMemcpyDeviceToDevice, pop->st));
+    HIPC(pop, hipMemsetAsync(pop->vbuf[0], 0, sizeof(float4) * pop->total_slots, pop->st));
+    HIPC(pop, hipMemsetAsync(pop->diverged, 0, pop->R, pop->st));
+    pop->cur = 0;
+    HIPC(pop, hipMemcpyAsync(pop->xbuf[1], pop->xbuf[0], sizeof(float4) * pop->total_slots, hipMemcpyDeviceToDevice,
+                             pop->st));
+    HIPC(pop, hipMemcpyAsync(pop->vbuf[1], pop->vbuf[0], sizeof(float4) * pop->total_slots, hipMemcpyDeviceToDevice,
+                             pop->st));
+    pop->h_step = 0;
+    pop->h_step_stage = 0;
+    HIPC(pop, hipMemcpyAsync(pop->d_step, &pop->h_step_stage, sizeof(int64_t), hipMemcpyHostToDevice, pop->st));
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    pop->rec_valid = pop->ck_every > 0;
+    return SR_OK;
+}
+
+int pop_record(sr_pop *pop, int32_t checkpoint_every, int32_t max_steps) {
+    CHECK_POP(pop);
+    if (checkpoint_every < 0 || max_steps < 0) return set_err(SR_EINVAL, "negative checkpoint interval or horizon");
+    if (pop->ck_x) HIPC(pop, hipStreamSynchronize(pop->st));
+    if (pop->ck_x) HIPC(pop, hipFree(pop->ck_x));
+    if (pop->ck_v) HIPC(pop, hipFree(pop->ck_v));
+    pop->ck_x = pop->ck_v = nullptr;
+    pop->ck_every = 0;
+    pop->ck_cap = 0;
+    pop->rec_valid = false;
+    if (checkpoint_every == 0) return SR_OK;
+    const int cap = max_steps / checkpoint_every + 1;
+    hipError_t e = dalloc(&pop->ck_x, (size_t)cap * pop->total_slots);
+    if (e == hipSuccess) e = dalloc(&pop->ck_v, (size_t)cap * pop->total_slots);
+    if (e != hipSuccess) return set_err(SR_ENOMEM, "checkpoint storage: %s", hipGetErrorString(e));
+    pop->ck_every = checkpoint_every;
+    pop->ck_cap = cap;
+    pop->rec_valid = pop->built && pop->h_step == 0;
+    return SR_OK;
+}
+
+namespace {
+int ensure_adj_scratch(sr_pop *pop, int K) {
+    if (K <= pop->rec_cap) return SR_OK;
+    HIPC(pop, hipStreamSynchronize(pop->st));
+    void *old[] = {pop->rec_x, pop->rec_v, pop->tmp_x, pop->tmp_v, pop->lx, pop->lv, pop->gk, pop->gs, pop->gc,
+                   pop->dJdw, pop->sc_seg};
+    for (void *p : old)
+        if (p) HIPC(pop, hipFree(p));
+    const size_t S = pop->total_slots;
+    hipError_t e = dalloc(&pop->rec_x, S * K);
+    if (e == hipSuccess) e = dalloc(&pop->rec_v, S * K);
+    if (e == hipSuccess) e = dalloc(&pop->tmp_x, S);
+    if (e == hipSuccess) e = dalloc(&pop->tmp_v, S);
+    if (e == hipSuccess) e = dalloc(&pop->lx, S);
+    if (e == hipSuccess) e = dalloc(&pop->lv, S);
+    if (e == hipSuccess) e = dalloc(&pop->gk, S * NDIR);
+    if (e == hipSuccess) e = dalloc(&pop->gs, S * NDIR);
+    if (e == hipSuccess) e = dalloc(&pop->gc, S * NDIR);
+    if (e == hipSuccess) e = dalloc(&pop->dJdw, (size_t)pop->total_vox);
+    if (e == hipSuccess) e = dalloc(&pop->sc_seg, (size_t)K);
+    if (e != hipSuccess) {
+        pop->rec_cap = 0;
+        return set_err(SR_ENOMEM, "adjoint scratch: %s", hipGetErrorString(e));
+    }
+    pop->rec_cap = K;
+    return SR_OK;
+}
+}  // namespace
+
+int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, float *g_phi, const float *genomes,
+                 const float *B, float *g_genome) {
+    CHECK_POP(pop);
+    if (!dJ_dfitness) return set_err(SR_EINVAL, "null dJ/dfitness");
+    if (!pop->built) return set_err(SR_ESTATE, "pop_backward before a build");
+    if (!pop->rec_valid || pop->ck_every <= 0)
+        return set_err(SR_ESTATE, "no recorded run: call pop_record right after the build, then pop_step");
+    if (g_genome && (!genomes || !B)) return set_err(SR_EINVAL, "genome gradient needs the genomes and B");
+    if (g_genome)
+        for (int c = 0; c < 5; ++c)
+            if (pop->p.phi_class[c] != 0.f)
+                return set_err(SR_EUNSUPPORTED, "genome gradient needs every class phase to be zero");
+    for (const auto &gr : pop->groups)
+        if (gr.n > 11) return set_err(SR_EUNSUPPORTED, "no adjoint kernel for side %d", gr.n);
+    const int K = pop->ck_every;
+    int rc = ensure_adj_scratch(pop, K);
+    if (rc) return rc;
+    rc = ensure_counts(pop);
+    if (rc) return rc;
+    const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
+    HIPC(pop, launch_adj_init(pop->d_robots, pop->total_slots, pop->slot_robot, pop->x0, dJ_dfitness, pop->lx, pop->lv,
+                              pop->gk, pop->gs, pop->gc, pop->st));
+    const int64_t T = pop->h_step;
+    const int nseg = (int)((T + K - 1) / K);
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t s0 = (int64_t)seg * K;
+        const int len = (int)((T - s0) < K ? (T - s0) : K);
+        const size_t off = (size_t)seg * pop->total_slots;
+        HIPC(pop, hipMemcpyAsync(pop->tmp_x, pop->ck_x + off, sizeof(float4) * pop->total_slots,
+                                 hipMemcpyDeviceToDevice, pop->st));
+        HIPC(pop, hipMemcpyAsync(pop->tmp_v, pop->ck_v + off, sizeof(float4) * pop->total_slots,
+                                 hipMemcpyDeviceToDevice, pop->st));
+        HIPC(pop, launch_sincos_at(pop->sc_seg, s0, len, omega_dt, pop->c.actuation, pop->st));
+        for (const auto &gr : pop->groups)
+            HIPC(pop, launch_record(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count, pop->pl,
+                                    pop->tmp_x, pop->tmp_v, pop->sc_seg, len, pop->diverged, pop->c, pop->rec_x,
+                                    pop->rec_v, pop->st));
+        for (const auto &gr : pop->groups)
+            HIPC(pop, launch_adjoint(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count, pop->pl,
+                                     pop->x0, pop->rec_x, pop->rec_v, len, pop->sc_seg, pop->lx, pop->lv, pop->gk,
+                                     pop->gs, pop->gc, pop->c, pop->st));
+    }
+    HIPC(pop, launch_adj_springs(pop->d_robots, pop->total_slots, pop->slot_robot, pop->sid, pop->d_spring_off, pop->pl,
+                                 pop->p.voxel_len, pop->gk, pop->gs, pop->gc, g_k, g_a, g_phi, pop->st));
+    if (g_genome)
+        HIPC(pop, launch_adj_genome(pop->d_robots, pop->R, pop->total_vox, pop->vox_robot, pop->kept, pop->pl, pop->gk,
+                                    pop->gs, pop->p, genomes, B, pop->dJdw, g_genome, pop->st));
     return SR_OK;
 }
 

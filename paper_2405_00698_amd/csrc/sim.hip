@@ -40,6 +40,19 @@ __global__ void k_sincos(float2 *sc, const int64_t *d_step, int n, double omega_
     sc[i] = make_float2((float)s, (float)c);
 }
 
+__global__ void k_sincos_at(float2 *sc, int64_t step0, int n, double omega_dt, int on) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (!on) {
+        sc[i] = make_float2(0.f, 0.f);
+        return;
+    }
+    const double arg = omega_dt * (double)(step0 + i);
+    double s, c;
+    sincos(arg, &s, &c);
+    sc[i] = make_float2((float)s, (float)c);
+}
+
 __global__ void k_advance(int64_t *d_step, int n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *d_step += n;
 }
@@ -135,14 +148,9 @@ struct PArgs {
     int n_steps;
     uint8_t *diverged;
     SimConst c;
-};
-
-template <int N>
-struct Geo {
-    static constexpr int SL = N * N * N;
-    static constexpr int PAD = N * N + N + 1;
-    static constexpr int XL = SL + 2 * PAD;
-    static constexpr int CL = SL + PAD;
+    // recording form: per step the positions x_n and the pre-friction velocity v'_n
+    // of every slot, at rec_x[n_steps * slot_base + t * slots + s]
+    float4 *rec_x, *rec_v;
 };
 
 template <int N, int BS, int VAR>
@@ -152,7 +160,7 @@ constexpr size_t lds_bytes() {
     return 2 * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL;
 }
 
-template <int N, int BS, int VAR, bool FENCE, bool PHASE>
+template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
@@ -330,7 +338,10 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
             for (int k = 0; k < NPT; ++k) {
                 const int s = tid + k * BS;
                 if (pres[k]) {
-                    integrate_node(c, xr[k], vr[k], Ff[k], Fb[k]);
+                    float3 vp;
+                    if (REC) A.rec_x[(size_t)A.n_steps * base + (size_t)t * SL + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
+                    integrate_node(c, xr[k], vr[k], Ff[k], Fb[k], REC ? &vp : nullptr);
+                    if (REC) A.rec_v[(size_t)A.n_steps * base + (size_t)t * SL + s] = make_float4(vp.x, vp.y, vp.z, 0.f);
                     xn[PAD + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
                 }
             }
@@ -484,6 +495,15 @@ const PersistEntry kPersist[] = {
     SR_PE(12, 768, 2, 1), SR_PE(12, 768, 0, 0), SR_PE(12, 1024, 2, 0), SR_PE(12, 1024, 2, 1),
 };
 
+#define SR_REC(NN, BS, VAR) \
+    { NN, BS, VAR, k_persist<NN + 1, BS, VAR, false, false, true>, k_persist<NN + 1, BS, VAR, false, true, true>, 0 }
+
+// recording forms (used to recompute checkpointed segments for the adjoint)
+const PersistEntry kRec[] = {
+    SR_REC(1, 64, 1),   SR_REC(2, 64, 1),  SR_REC(3, 64, 1),  SR_REC(4, 128, 1),  SR_REC(5, 256, 1),  SR_REC(6, 384, 1),
+    SR_REC(7, 512, 1),  SR_REC(8, 768, 0), SR_REC(9, 1024, 1), SR_REC(10, 448, 1), SR_REC(11, 896, 1), SR_REC(12, 768, 2),
+};
+
 const PersistEntry *find_persist(const PersistCfg &cfg) {
     for (const auto &e : kPersist)
         if (e.n == cfg.n && e.block == cfg.block && e.variant == cfg.variant) return &e;
@@ -528,14 +548,46 @@ hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo 
     A.n_steps = n_steps;
     A.diverged = diverged;
     A.c = c;
+    A.rec_x = nullptr;
+    A.rec_v = nullptr;
     PersistFn fn = phase ? e->fn_phase : e->fn;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(e->block), 0, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_record(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
+                         float4 *x, float4 *v, const float2 *sc, int n_steps, uint8_t *diverged, SimConst c,
+                         float4 *rec_x, float4 *rec_v, hipStream_t st) {
+    const PersistEntry *e = nullptr;
+    for (const auto &q : kRec)
+        if (q.n == n) e = &q;
+    if (!e) return hipErrorInvalidConfiguration;
+    PArgs A;
+    A.robots = robots;
+    A.list = list;
+    A.count = count;
+    A.pl = pl;
+    A.x = x;
+    A.v = v;
+    A.sc = sc;
+    A.n_steps = n_steps;
+    A.diverged = diverged;
+    A.c = c;
+    A.rec_x = rec_x;
+    A.rec_v = rec_v;
+    hipLaunchKernelGGL(phase ? e->fn_phase : e->fn, dim3(count), dim3(e->block), 0, st, A);
     return hipGetLastError();
 }
 
 hipError_t launch_sincos(float2 *sc, const int64_t *d_step, int n, double omega_dt, int on, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sincos, dim3((n + 255) / 256), dim3(256), 0, st, sc, d_step, n, omega_dt, on);
+    return hipGetLastError();
+}
+
+hipError_t launch_sincos_at(float2 *sc, int64_t step0, int n, double omega_dt, int on, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sincos_at, dim3((n + 255) / 256), dim3(256), 0, st, sc, step0, n, omega_dt, on);
     return hipGetLastError();
 }
 

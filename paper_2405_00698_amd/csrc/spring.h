@@ -7,6 +7,18 @@
 
 namespace sr {
 
+// Dense lattice of a robot with side n (N = n + 1 points per side) as held in
+// LDS: SL slots, PAD ghost slots before and after (the largest stencil offset
+// is N^2 + N + 1), XL = SL + 2 PAD; CL is one coefficient row (PAD zero
+// entries in front of SL slot entries).
+template <int N>
+struct Geo {
+    static constexpr int SL = N * N * N;
+    static constexpr int PAD = N * N + N + 1;
+    static constexpr int XL = SL + 2 * PAD;
+    static constexpr int CL = SL + PAD;
+};
+
 // Hooke spring with actuated rest length L(t) = L0 (1 + a sin(w t + phi)):
 // the force on the lower endpoint is k (r - L) d / r = (k - k L / r) d, with
 // d = x_upper - x_lower.  k L = kL0 + kal S + kbe C with (S, C) = (sin, cos)(w t).
@@ -39,12 +51,14 @@ __device__ __forceinline__ float len2(float dx, float dy, float dz) { return fma
 // One node's update from its total spring force (forward-direction sum Ff and
 // backward-direction sum Fb, added in that order): gravity, ground normal,
 // semi-implicit Euler, velocity-level Coulomb friction, damping.
-__device__ __forceinline__ void integrate_node(const SimConst &c, float3 &x, float3 &v, float3 Ff, float3 Fb) {
+__device__ __forceinline__ void integrate_node(const SimConst &c, float3 &x, float3 &v, float3 Ff, float3 Fb,
+                                               float3 *vprime = nullptr) {
     float Fx = Ff.x + Fb.x, Fy = Ff.y + Fb.y, Fz = Ff.z + Fb.z;
     const bool below = c.ground && x.z < 0.f;
     if (c.gravity) Fz -= c.mg;
     if (below) Fz = fmaf(c.kc, -x.z, Fz);
     float vx = fmaf(c.dt_m, Fx, v.x), vy = fmaf(c.dt_m, Fy, v.y), vz = fmaf(c.dt_m, Fz, v.z);
+    if (vprime) *vprime = make_float3(vx, vy, vz);
     if (below) {
         const float dv = c.mu_kc_dt_m * (-x.z);
         const float u = sqrtf(fmaf(vy, vy, vx * vx));

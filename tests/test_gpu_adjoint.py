@@ -1,0 +1,156 @@
+"""GPU checkpointed adjoint (FP32) against the FP64 oracle's adjoint, which
+is itself pinned to central finite differences on the CPU.  Gradients are
+compared per parameter group by relative L2 error, at the horizon where the
+forward meets parity with contact (200 steps)."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, gpu_population, need_gpu, oracle_robots, say, voxel_population
+from paper_2405_00698_amd import SR_QUERY_FP32, inputs
+
+pytestmark = pytest.mark.gpu
+
+C1 = [4] * 8
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _l2rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _dJ(R, seed=0):
+    return np.random.default_rng(seed).uniform(0.5, 1.5, size=R).astype(np.float32)
+
+
+def test_spring_gradients_match_oracle(orc):
+    cls, w = voxel_population(C1, 51)
+    steps, K = 200, 50
+    P = gpu_population(C1, cls, w)
+    P.record(K, steps)
+    P.step(steps)
+    dJ = _dJ(len(C1))
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in P.backward(torch.from_numpy(dJ).to(DEV)).items()}
+    M, S, mo, so = P.counts()
+    robots = oracle_robots(orc, C1, cls, w)
+    errs = []
+    for r, R in enumerate(robots):
+        J, gk, ga, gp = R.backward(steps, g=float(dJ[r]))
+        sl = slice(so[r], so[r + 1])
+        e = (_l2rel(g["k"][sl], gk), _l2rel(g["a"][sl], ga), _l2rel(g["phi"][sl], gp))
+        errs.append(e)
+    say("per-robot relative L2 errors (k, a, phi):", [tuple("%.1e" % v for v in e) for e in errs])
+    assert max(max(e) for e in errs) < 1e-2
+
+
+def test_gradients_independent_of_checkpoint_interval():
+    cls, w = voxel_population(C1, 52)
+    steps = 200
+    ref = None
+    dJ = torch.from_numpy(_dJ(len(C1), 1)).to(DEV)
+    for K in (1, 7, 64, 200):
+        P = gpu_population(C1, cls, w)
+        P.record(K, steps)
+        P.step(steps)
+        g = {k: v.cpu().numpy() for k, v in P.backward(dJ).items()}
+        if ref is None:
+            ref = g
+        else:
+            for key in ("k", "a", "phi"):
+                assert np.array_equal(g[key], ref[key]), (K, key)
+
+
+def test_genome_gradient_matches_oracle(orc):
+    sides = [3] * 6
+    B = inputs.gaussian_B()
+    G = inputs.random_genomes(6, seed=5)
+    steps, K = 150, 50
+    from paper_2405_00698_amd.api import Population
+    P = Population(sides)
+    Gt, Bt = torch.from_numpy(G).to(DEV), torch.from_numpy(B).to(DEV)
+    P.build_from_genomes(Gt, Bt, SR_QUERY_FP32)
+    P.record(K, steps)
+    P.step(steps)
+    dJ = _dJ(6, 2)
+    gg = P.backward(torch.from_numpy(dJ).to(DEV), genomes=Gt, B=Bt)["genome"].cpu().numpy().astype(np.float64)
+    for r in range(6):
+        lg = orc.query(G[r].astype(np.float64), B.astype(np.float64), 3)
+        srt = np.sort(lg[:, :5], axis=1)
+        if (srt[:, -1] - srt[:, -2]).min() <= 1e-4:
+            continue
+        J, go = orc.genome_fitness_grad(G[r].astype(np.float64), B.astype(np.float64), 3, steps)
+        go = go * float(dJ[r])
+        e = _l2rel(gg[r], go)
+        say("robot", r, "genome gradient relative L2 %.2e" % e)
+        assert e < 2e-2
+
+
+def test_autograd_functions_route_through_the_adjoint():
+    from paper_2405_00698_amd.api import GenomeFitness, Population, SpringFitness
+    cls, w = voxel_population(C1, 53)
+    P = gpu_population(C1, cls, w)
+    sp = P.springs()
+    k = sp["k"].clone().requires_grad_(True)
+    a = sp["a"].clone().requires_grad_(True)
+    phi = sp["phi"].clone().requires_grad_(True)
+    wts = torch.from_numpy(_dJ(8, 3)).to(DEV)
+    fit = SpringFitness.apply(k, a, phi, P, 120, 40)
+    (fit * wts).sum().backward()
+    P2 = gpu_population(C1, cls, w)
+    P2.set_spring_params(k.detach(), a.detach(), phi.detach())
+    P2.record(40, 120)
+    P2.step(120)
+    g = P2.backward(wts)
+    assert torch.equal(k.grad, g["k"]) and torch.equal(a.grad, g["a"]) and torch.equal(phi.grad, g["phi"])
+    # genome path
+    B = torch.from_numpy(inputs.gaussian_B()).to(DEV)
+    G = torch.from_numpy(inputs.random_genomes(4, seed=9)).to(DEV).requires_grad_(True)
+    P3 = Population([4] * 4)
+    f3 = GenomeFitness.apply(G, B, P3, 100, 25)
+    f3.sum().backward()
+    assert G.grad is not None and torch.isfinite(G.grad).all() and G.grad.abs().sum() > 0
+
+
+def test_backward_without_recording_is_an_error():
+    from paper_2405_00698_amd import _lib
+    cls, w = voxel_population(C1, 54)
+    P = gpu_population(C1, cls, w)
+    P.step(10)
+    with pytest.raises(_lib.SoftRobotError):
+        P.backward(torch.ones(8, device=DEV))
+
+
+def test_adjoint_forward_time_ratio_c4():
+    """64 robots of 8^3, 2000 steps, checkpoint every 100: time of pop_backward
+    (recompute included) over the forward pop_step(2000)."""
+    sides = [8] * 64
+    B = torch.from_numpy(inputs.gaussian_B()).to(DEV)
+    G = torch.from_numpy(inputs.random_genomes(64, seed=1)).to(DEV)
+    from paper_2405_00698_amd.api import Population
+    P = Population(sides)
+    P.build_from_genomes(G, B, SR_QUERY_FP32)
+    P.record(100, 2000)
+    P.step(200)
+    torch.cuda.synchronize()
+    P.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.step(2000)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    dJ = torch.ones(64, device=DEV)
+    P.backward(dJ)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = P.backward(dJ)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    say("C4 forward %.4f s  backward %.4f s  ratio %.2f" % (tf, tb, tb / tf))
+    assert torch.isfinite(g["k"]).all()
+    assert tb / tf < 10.0
