@@ -31,6 +31,23 @@ VALU_SLOTS_PER_SPRING = 18.0                 # one force evaluation applied to b
 VALU_SLOTS_PER_MASS = 20.0                   # gravity, ground, friction, damping, integrate
 
 
+def measured_traffic(kernel_cfg, sim_steps):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by a copy probe), or None when the
+    kernel source or the launch differs from the one measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    h = hashlib.sha256()
+    for f in d["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != d["source_sha256"] or d["launch_steps"] != sim_steps or d["kernel"] != kernel_cfg:
+        return None
+    return d["hbm_bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +61,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=5000)
     ap.add_argument("--cpu-robots", type=int, default=64)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the per-step-launch baseline and the adjoint/forward ratio")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device copy (HBM counter calibration under rocprofv3)")
     return ap.parse_args()
 
 
@@ -62,6 +83,53 @@ def cpu_baseline(args, genomes, B):
             "kind": "oracle",
             "sample": "%d robots of %d^3 from the same genomes, %d steps, FP64, one robot per thread (%.1f s)"
                       % (args.cpu_robots, args.side, args.cpu_steps, dt)}
+
+
+def plain_baseline(api, inputs, torch, R, n, steps, prec):
+    """The same workload stepped by the per-step-launch kernel (state in HBM)."""
+    from paper_2405_00698_amd import SR_STEP_PLAIN
+    dev = torch.device("cuda:0")
+    P = api.Population([n] * R)
+    P.set_step_config(SR_STEP_PLAIN)
+    P.build_from_genomes(torch.from_numpy(inputs.random_genomes(R)).to(dev),
+                         torch.from_numpy(inputs.gaussian_B()).to(dev), prec)
+    S = sum(P.counts()[1])
+    P.step(20)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    P.close()
+    return S * steps / dt
+
+
+def adjoint_ratio(api, inputs, torch):
+    """64 robots of 8^3, 2000 steps, checkpoint every 100 steps: pop_backward
+    (segment recompute included) over the forward pop_step(2000)."""
+    from paper_2405_00698_amd import SR_QUERY_FP32
+    dev = torch.device("cuda:0")
+    P = api.Population([8] * 64)
+    P.build_from_genomes(torch.from_numpy(inputs.random_genomes(64)).to(dev),
+                         torch.from_numpy(inputs.gaussian_B()).to(dev), SR_QUERY_FP32)
+    P.record(100, 2000)
+    dJ = torch.ones(64, device=dev)
+    tf, tb = [], []
+    for _ in range(3):
+        P.reset()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P.step(2000)
+        torch.cuda.synchronize()
+        tf.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        P.backward(dJ)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t)
+    P.close()
+    f, b = float(np.median(tf)), float(np.median(tb))
+    return {"value": b / f, "forward_s": f, "backward_s": b,
+            "workload": "64 robots of 8^3, 2000 steps, checkpoint every 100, FP32"}
 
 
 def main():
@@ -150,10 +218,24 @@ def main():
         "sim_kernel_s": kern_s,
         "sim_spring_updates_per_s": su_per_launch / kern_s,
         "roofline": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                     "frac": lds_gbs / LDS_PEAK_GBS, "traffic": None},
+                     "frac": lds_gbs / LDS_PEAK_GBS,
+                     "traffic": measured_traffic(P.kernel_config(n), args.sim_steps) if args.mode == "persistent"
+                     else None},
         "roofline_alu": {"bound": "alu", "achieved": valu / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                          "unit": "T lane-op slots/s", "frac": valu / VALU_PEAK_SLOTS},
     }
+    if args.copy_probe:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 4
+    if not args.no_extras:
+        P.close()
+        pl = plain_baseline(api, inputs, torch, R, n, 500, prec)
+        out["per_step_launch_spring_updates_per_s"] = pl
+        out["persistent_over_per_step_launch"] = (su_per_launch / kern_s) / pl
+        out["adjoint_forward_ratio"] = adjoint_ratio(api, inputs, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, G, B)
     print(json.dumps(out), flush=True)

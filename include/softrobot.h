@@ -135,6 +135,16 @@ int pop_build_from_genomes(sr_pop *pop, const float *genomes, const float *B, in
  * default values.  SR_EUNSUPPORTED for a configuration the kernels lack. */
 int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_per_launch);
 
+/* Lists the persistent kernel configurations compiled for side n: writes up
+ * to cap (block, variant) pairs (host arrays, may be NULL when cap is 0) and
+ * returns how many exist (>= 0), or SR_EINVAL. */
+int sr_persist_configs(int32_t n, int32_t *blocks, int32_t *variants, int32_t cap);
+
+/* Steps without checkpoints run as captured HIP graphs (one per step count,
+ * step form and state buffer), with one parallel branch per grid side;
+ * enable = 0 launches the kernels directly instead.  On by default. */
+int pop_set_graphs(sr_pop *pop, int32_t enable);
+
 /* Picks the persistent kernel for robots of side n: block threads per
  * workgroup and variant (0 recompute every spring force at both ends,
  * 1 exchange spring coefficients through LDS, 2 exchange in two direction
@@ -142,6 +152,8 @@ int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_
  * give bit-identical results.  SR_EUNSUPPORTED for a combination the library
  * lacks. */
 int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t variant);
+/* The persistent kernel configuration in use for side n (host outputs). */
+int pop_get_persist_variant(sr_pop *pop, int32_t n, int32_t *block, int32_t *variant);
 
 /* Advances every robot n_steps >= 0 steps.  Step n -> n+1 (t_n = n dt):
  * spring forces k (r - L(t_n)) along each spring with L = L0 (1 + a sin(2 pi f

@@ -57,6 +57,9 @@ _SIGS = {
     "pop_get_status": ([P, P], C.c_int),
     "pop_set_persist_variant": ([P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "pop_reset": ([P], C.c_int),
+    "pop_set_graphs": ([P, C.c_int32], C.c_int),
+    "sr_persist_configs": ([C.c_int32, P, P, C.c_int32], C.c_int),
+    "pop_get_persist_variant": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "pop_record": ([P, C.c_int32, C.c_int32], C.c_int),
     "pop_backward": ([P, P, P, P, P, P, P, P], C.c_int),
     "ga_generation": ([P, P, P, C.c_int32, C.c_int32, C.POINTER(GAParams), C.c_uint64, C.c_uint64, P, P],

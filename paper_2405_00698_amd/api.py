@@ -76,6 +76,18 @@ class Population:
     def set_persist_variant(self, n, block, variant):
         check(_lib.load().pop_set_persist_variant(self.h, int(n), int(block), int(variant)))
 
+    def set_graphs(self, enable):
+        check(_lib.load().pop_set_graphs(self.h, 1 if enable else 0))
+
+    def persist_variant(self, n):
+        b, v = C.c_int32(), C.c_int32()
+        check(_lib.load().pop_get_persist_variant(self.h, int(n), C.byref(b), C.byref(v)))
+        return b.value, v.value
+
+    def kernel_config(self, n):
+        b, v = self.persist_variant(n)
+        return "k_persist<%d, %d, %d>" % (n + 1, b, v)
+
     def step(self, n_steps):
         check(_lib.load().pop_step(self.h, int(n_steps)))
 
@@ -168,6 +180,18 @@ class Population:
         out = torch.empty(self.R, dtype=torch.uint8, device=self.device)
         check(_lib.load().pop_get_status(self.h, _ptr(out, torch.uint8)))
         return out
+
+
+def persist_configs(n):
+    """(block, variant) persistent-kernel configurations compiled for side n."""
+    L = _lib.load()
+    cnt = L.sr_persist_configs(int(n), None, None, 0)
+    if cnt < 0:
+        check(cnt)
+    b = (C.c_int32 * max(cnt, 1))()
+    v = (C.c_int32 * max(cnt, 1))()
+    L.sr_persist_configs(int(n), b, v, cnt)
+    return [(b[i], v[i]) for i in range(cnt)]
 
 
 def prob_threshold(p):

@@ -120,6 +120,7 @@ struct PersistCfg {
 };
 bool persist_supported(const PersistCfg &cfg, bool phase);
 int persist_default_block(int n, int *variant);
+int persist_list(int n, int32_t *blocks, int32_t *variants, int cap);
 size_t persist_lds_bytes(const PersistCfg &cfg);
 hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo *robots, const int32_t *list,
                              int count, int grid, Planes pl, float4 *x, float4 *v, const float2 *sc,

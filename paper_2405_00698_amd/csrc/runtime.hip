@@ -30,6 +30,16 @@ struct SideGroup {
     PersistCfg cfg;
 };
 
+struct GraphKey {
+    int n_steps, mode, cur, spl;
+    bool operator<(const GraphKey &o) const {
+        if (n_steps != o.n_steps) return n_steps < o.n_steps;
+        if (mode != o.mode) return mode < o.mode;
+        if (cur != o.cur) return cur < o.cur;
+        return spl < o.spl;
+    }
+};
+
 struct sr_pop {
     sr_sim_params p;
     SimConst c;
@@ -74,6 +84,12 @@ struct sr_pop {
     float4 *rec_x = nullptr, *rec_v = nullptr, *tmp_x = nullptr, *tmp_v = nullptr, *lx = nullptr, *lv = nullptr;
     float *gk = nullptr, *gs = nullptr, *gc = nullptr, *dJdw = nullptr;
     float2 *sc_seg = nullptr;
+    // captured step graphs: one per (n_steps, mode, current buffer, steps per launch)
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;
+    std::map<GraphKey, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -102,7 +118,16 @@ hipError_t dalloc(T **p, size_t count) {
     return hipMalloc(reinterpret_cast<void **>(p), sizeof(T) * count);
 }
 
+void clear_graphs(sr_pop *pop) {
+    for (auto &kv : pop->graphs) (void)hipGraphExecDestroy(kv.second);
+    pop->graphs.clear();
+}
+
 void pop_free(sr_pop *pop) {
+    clear_graphs(pop);
+    for (auto s : pop->side) (void)hipStreamDestroy(s);
+    for (auto e : pop->ev) (void)hipEventDestroy(e);
+    if (pop->cap) (void)hipStreamDestroy(pop->cap);
     void *ptrs[] = {pop->d_robots, pop->kept, pop->w, pop->pl.k, pop->pl.kL0, pop->pl.kal, pop->pl.kbe,
                     pop->sid, pop->x0, pop->xbuf[0], pop->xbuf[1], pop->vbuf[0], pop->vbuf[1],
                     pop->slot_node, pop->node_slot, pop->slot_robot, pop->rows, pop->entries,
@@ -139,6 +164,7 @@ int ensure_sc(sr_pop *pop, int n) {
     HIPC(pop, hipStreamSynchronize(pop->st));
     if (pop->sc) HIPC(pop, hipFree(pop->sc));
     pop->sc = nullptr;
+    clear_graphs(pop);  // graphs hold the old table address
     int cap = n < 1024 ? 1024 : n;
     HIPC(pop, dalloc(&pop->sc, (size_t)cap));
     pop->sc_cap = cap;
@@ -177,6 +203,11 @@ extern "C" {
 const char *sr_last_error(void) { return g_err.c_str(); }
 
 int sr_version(void) { return 1; }
+
+int sr_persist_configs(int32_t n, int32_t *blocks, int32_t *variants, int32_t cap) {
+    if (n < 1 || n > SR_MAX_SIDE) return set_err(SR_EINVAL, "side %d outside 1..%d", n, SR_MAX_SIDE);
+    return persist_list(n, blocks, variants, cap < 0 ? 0 : cap);
+}
 
 int sr_default_params(sr_sim_params *out) {
     if (!out) return set_err(SR_EINVAL, "null output");
@@ -296,8 +327,22 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
         pop->groups.push_back(g);
     }
     int rc = SR_OK;
-    e = hipMemcpyAsync(pop->d_robots, pop->h_robots.data(), sizeof(RobotInfo) * n_robots, hipMemcpyHostToDevice,
-                       pop->st);
+    // private streams (default priority) for capturing step graphs: one per
+    // extra size group, so the groups become parallel branches of one graph
+    e = hipStreamCreateWithFlags(&pop->cap, hipStreamNonBlocking);
+    for (size_t g = 0; g + 1 < pop->groups.size() && e == hipSuccess; ++g) {
+        hipStream_t s2;
+        e = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+        if (e == hipSuccess) pop->side.push_back(s2);
+    }
+    for (size_t g = 0; g < 2 * pop->groups.size() && e == hipSuccess; ++g) {
+        hipEvent_t ev;
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e == hipSuccess) pop->ev.push_back(ev);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pop->d_robots, pop->h_robots.data(), sizeof(RobotInfo) * n_robots, hipMemcpyHostToDevice,
+                           pop->st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(pop->slot_robot, slot_robot.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, pop->st);
     if (e == hipSuccess)
@@ -351,6 +396,7 @@ int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_
     if (mode < SR_STEP_AUTO || mode > SR_STEP_PLAIN) return set_err(SR_EINVAL, "unknown step mode %d", mode);
     pop->mode = mode;
     pop->spl = steps_per_launch > 0 ? steps_per_launch : 0;
+    clear_graphs(pop);
     if (block > 0) {
         for (auto &g : pop->groups) {
             bool found = false;
@@ -376,9 +422,74 @@ int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t varia
             if (!persist_supported(c, pop->phase))
                 return set_err(SR_EUNSUPPORTED, "no persistent kernel for n=%d block=%d variant=%d", n, block, variant);
             g.cfg = c;
+            clear_graphs(pop);
             return SR_OK;
         }
     return set_err(SR_EINVAL, "no robot of side %d", n);
+}
+
+int pop_get_persist_variant(sr_pop *pop, int32_t n, int32_t *block, int32_t *variant) {
+    CHECK_POP(pop);
+    for (const auto &g : pop->groups)
+        if (g.n == n) {
+            if (block) *block = g.cfg.block;
+            if (variant) *variant = g.cfg.variant;
+            return SR_OK;
+        }
+    return set_err(SR_EINVAL, "no robot of side %d", n);
+}
+
+namespace {
+// Enqueues n_steps on stream st without checkpoints: the time table, then the
+// step kernels (persistent: one launch per size group and block of steps, the
+// groups on their own streams so they run side by side; plain: one launch per
+// step), then the step counter.  Used eagerly and under graph capture.
+int enqueue_steps(sr_pop *pop, int n_steps, hipStream_t st) {
+    const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
+    HIPC(pop, launch_sincos(pop->sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, st));
+    const int spl = pop->spl > 0 ? pop->spl : n_steps;
+    if (pop->mode == SR_STEP_PLAIN) {
+        for (int t = 0; t < n_steps; ++t) {
+            const int a = pop->cur, b = 1 - pop->cur;
+            HIPC(pop, launch_plain_step(pop->d_robots, pop->R, pop->total_slots, pop->rows, pop->entries, pop->pl,
+                                        pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], pop->sc, t,
+                                        pop->phase, pop->diverged, pop->slot_robot, pop->c, st));
+            pop->cur = b;
+        }
+        HIPC(pop, launch_check_div(pop->d_robots, pop->R, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->diverged,
+                                   pop->c.lim, st));
+    } else {
+        const int G = (int)pop->groups.size();
+        if (G > 1) {
+            HIPC(pop, hipEventRecord(pop->ev[0], st));
+            for (int g = 1; g < G; ++g) HIPC(pop, hipStreamWaitEvent(pop->side[g - 1], pop->ev[0], 0));
+        }
+        // largest robots first: group G-1 has the largest side
+        for (int t0 = 0; t0 < n_steps; t0 += spl) {
+            const int cnt = (n_steps - t0) < spl ? (n_steps - t0) : spl;
+            for (int q = 0; q < G; ++q) {
+                const SideGroup &gr = pop->groups[G - 1 - q];
+                hipStream_t sq = q == 0 ? st : pop->side[q - 1];
+                HIPC(pop, launch_persistent(gr.cfg, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count,
+                                            gr.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur],
+                                            pop->sc + t0, cnt, pop->diverged, pop->c, sq));
+            }
+        }
+        for (int q = 1; q < G; ++q) {
+            HIPC(pop, hipEventRecord(pop->ev[q], pop->side[q - 1]));
+            HIPC(pop, hipStreamWaitEvent(st, pop->ev[q], 0));
+        }
+    }
+    HIPC(pop, launch_advance(pop->d_step, n_steps, st));
+    return SR_OK;
+}
+}  // namespace
+
+int pop_set_graphs(sr_pop *pop, int32_t enable) {
+    CHECK_POP(pop);
+    pop->use_graphs = enable != 0;
+    if (!pop->use_graphs) clear_graphs(pop);
+    return SR_OK;
 }
 
 int pop_step(sr_pop *pop, int32_t n_steps) {
@@ -388,6 +499,38 @@ int pop_step(sr_pop *pop, int32_t n_steps) {
     if (n_steps == 0) return SR_OK;
     int rc = ensure_sc(pop, n_steps);
     if (rc) return rc;
+    const bool recording = pop->rec_valid && pop->ck_every > 0;
+    if (!recording) {
+        if (!pop->use_graphs) {
+            rc = enqueue_steps(pop, n_steps, pop->st);
+            if (rc) return rc;
+        } else {
+            const GraphKey key{n_steps, pop->mode == SR_STEP_PLAIN ? 1 : 0, pop->cur, pop->spl};
+            auto it = pop->graphs.find(key);
+            const int cur0 = pop->cur;
+            if (it == pop->graphs.end()) {
+                HIPC(pop, hipStreamBeginCapture(pop->cap, hipStreamCaptureModeThreadLocal));
+                rc = enqueue_steps(pop, n_steps, pop->cap);
+                hipGraph_t graph = nullptr;
+                hipError_t e2 = hipStreamEndCapture(pop->cap, &graph);
+                if (rc) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return rc;
+                }
+                HIPC(pop, e2);
+                hipGraphExec_t exec = nullptr;
+                hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HIPC(pop, e3);
+                it = pop->graphs.emplace(key, exec).first;
+            }
+            // the graph carries the buffer flips of the per-step form
+            pop->cur = cur0 ^ ((pop->mode == SR_STEP_PLAIN) ? (n_steps & 1) : 0);
+            HIPC(pop, hipGraphLaunch(it->second, pop->st));
+        }
+        pop->h_step += n_steps;
+        return SR_OK;
+    }
     const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
     HIPC(pop, launch_sincos(pop->sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, pop->st));
     const int K = pop->rec_valid ? pop->ck_every : 0;

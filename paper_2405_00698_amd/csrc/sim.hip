@@ -523,6 +523,19 @@ size_t persist_lds_bytes(const PersistCfg &cfg) {
     return e ? e->lds : 0;
 }
 
+int persist_list(int n, int32_t *blocks, int32_t *variants, int cap) {
+    int cnt = 0;
+    for (const auto &e : kPersist)
+        if (e.n == n && e.lds <= 160 * 1024) {
+            if (cnt < cap) {
+                if (blocks) blocks[cnt] = e.block;
+                if (variants) variants[cnt] = e.variant;
+            }
+            ++cnt;
+        }
+    return cnt;
+}
+
 int persist_default_block(int n, int *variant) {
     for (const auto &e : kPersist)
         if (e.n == n && e.lds <= 160 * 1024) {

@@ -1,0 +1,79 @@
+"""Batching and launch machinery: captured step graphs (with one parallel
+branch per grid side) against direct launches, the tuner, and the uneven
+co-design loop (sides 4..12, BF16 query, GA) run end to end twice."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, gpu_population, need_gpu, say, voxel_population
+from paper_2405_00698_amd import SR_QUERY_BF16, SR_STEP_PLAIN, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_graphs_match_direct_launches_bitwise(plain):
+    sides = [int(n) for n in inputs.grid_sides(24, 4, 12)]
+    cls, w = voxel_population(sides, 61)
+    outs = []
+    for graphs in (True, False):
+        P = gpu_population(sides, cls, w)
+        if plain:
+            P.set_step_config(SR_STEP_PLAIN)
+        P.set_graphs(graphs)
+        for n in (37, 37, 100, 1):    # repeated keys replay the cached graph
+            P.step(n)
+        x, v, st = P.state()
+        assert st == 175
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), P.fitness().cpu().numpy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_tuner_picks_a_compiled_config_and_keeps_results(tmp_path):
+    from paper_2405_00698_amd import tune, api
+    sides = [6] * 16 + [10] * 16
+    cls, w = voxel_population(sides, 62)
+    P = gpu_population(sides, cls, w)
+    P.step(150)
+    ref = P.state()[0].cpu().numpy()
+    res = tune.tune(P, steps=50, cache_path=str(tmp_path / "tune.json"), verbose=True)
+    for n, (b, v, t) in res.items():
+        assert (b, v) in api.persist_configs(n)
+        assert P.persist_variant(n) == (b, v)
+    P.step(150)
+    assert np.array_equal(P.state()[0].cpu().numpy(), ref)
+    res2 = tune.tune(P, steps=50, cache_path=str(tmp_path / "tune.json"))
+    assert {n: r[:2] for n, r in res.items()} == {n: r[:2] for n, r in res2.items()}
+
+
+def test_uneven_codesign_loop_is_reproducible():
+    """1024 robots with sides 4..12 and empty fractions spread 0.1..0.5:
+    build (BF16 MFMA) -> 500 steps -> fitness -> GA, three generations, twice."""
+    from paper_2405_00698_amd.api import GAConfig, Population, ga_generation
+    R = 1024
+    sides = [int(n) for n in inputs.grid_sides(R, 4, 12)]
+    B = torch.from_numpy(inputs.gaussian_B()).to(DEV)
+    G0 = inputs.random_genomes(R, seed=1, empty_bias=inputs.uniform(R, -0.2, 0.4, seed=2))
+    finals = []
+    for rep in range(2):
+        P = Population(sides)
+        G = [torch.from_numpy(G0).to(DEV), torch.empty((R, inputs.GENOME_LEN), device=DEV)]
+        fits = []
+        for g in range(3):
+            P.build_from_genomes(G[g % 2], B, SR_QUERY_BF16)
+            P.step(500)
+            f = P.fitness()
+            fits.append(f.cpu().numpy())
+            ga_generation(f, G[g % 2], G[(g + 1) % 2], GAConfig(), seed=3, generation=g)
+        finals.append((G[1].cpu().numpy(), np.array(fits)))
+        M, S, _, _ = P.counts()
+        say("uneven loop rep", rep, "mean springs %.0f max %d" % (np.mean(S), max(S)))
+        assert np.all(np.isfinite(fits[-1]))
+    assert np.array_equal(finals[0][0], finals[1][0])
+    assert np.array_equal(finals[0][1], finals[1][1])
