@@ -231,6 +231,12 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_extras:
+        peaks = {name: api.microbench(name) for name in ("lds_read_16B", "lds_read_12B", "lds_read_4B",
+                                                         "valu_fma", "valu_rsq")}
+        out["measured_peaks"] = {k: (v / 1e9 if k.startswith("lds") else v / 1e12) for k, v in peaks.items()}
+        out["measured_peaks"]["units"] = "LDS GB/s, VALU T lane-ops/s"
+        out["roofline"]["frac_of_measured_lds_12B"] = lds_gbs / out["measured_peaks"]["lds_read_12B"]
+        out["roofline_alu"]["frac_of_measured_fma"] = valu / peaks["valu_fma"]
         P.close()
         pl = plain_baseline(api, inputs, torch, R, n, 500, prec)
         out["per_step_launch_spring_updates_per_s"] = pl

@@ -135,6 +135,12 @@ int pop_build_from_genomes(sr_pop *pop, const float *genomes, const float *B, in
  * default values.  SR_EUNSUPPORTED for a configuration the kernels lack. */
 int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_per_launch);
 
+/* Roofline microbenchmark on the current device (synchronous): which = 0, 1,
+ * 2 LDS reads of 16, 12, 4 bytes per lane; 3 FP32 FMA; 4 v_rsq_f32.  Returns
+ * the time of one launch (*seconds) and its work (*units: bytes for LDS
+ * reads, lane operations for the VALU cases). */
+int sr_microbench(int32_t which, int32_t iters, double *seconds, double *units);
+
 /* Lists the persistent kernel configurations compiled for side n: writes up
  * to cap (block, variant) pairs (host arrays, may be NULL when cap is 0) and
  * returns how many exist (>= 0), or SR_EINVAL. */

@@ -58,6 +58,7 @@ _SIGS = {
     "pop_set_persist_variant": ([P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "pop_reset": ([P], C.c_int),
     "pop_set_graphs": ([P, C.c_int32], C.c_int),
+    "sr_microbench": ([C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "sr_persist_configs": ([C.c_int32, P, P, C.c_int32], C.c_int),
     "pop_get_persist_variant": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "pop_record": ([P, C.c_int32, C.c_int32], C.c_int),

@@ -194,6 +194,16 @@ def persist_configs(n):
     return [(b[i], v[i]) for i in range(cnt)]
 
 
+MICRO = {"lds_read_16B": 0, "lds_read_12B": 1, "lds_read_4B": 2, "valu_fma": 3, "valu_rsq": 4}
+
+
+def microbench(name, iters=4096):
+    """Measured rate of one roofline microbenchmark: bytes/s (LDS) or lane ops/s (VALU)."""
+    sec, units = C.c_double(), C.c_double()
+    check(_lib.load().sr_microbench(MICRO[name], int(iters), C.byref(sec), C.byref(units)))
+    return units.value / sec.value
+
+
 def prob_threshold(p):
     """floor(p * 2^64) as an unsigned 64-bit threshold (p in [0, 1])."""
     import math

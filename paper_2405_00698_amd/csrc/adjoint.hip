@@ -34,13 +34,21 @@ struct AArgs {
     SimConst c;
 };
 
-template <int N, int BS, bool PHASE>
+// XCH: each spring's K_s (lF_hi - lF_lo) is computed once by its lower end and
+// handed to the upper end through LDS (three rows per direction, PAD zero
+// entries in front); otherwise the upper end recomputes it.  Both give the
+// same bits.  The exchange keeps one position/adjoint buffer and adds a
+// barrier per step.
+template <int N, int BS, bool PHASE, bool XCH>
 __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     using G = Geo<N>;
-    constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL;
+    constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
-    __shared__ float4 xs[2][XL];
-    __shared__ float4 lf[2][XL];
+    constexpr int NBUF = XCH ? 1 : 2;
+    constexpr int NQ = XCH ? 1 : NDIR;
+    __shared__ float4 xs[NBUF][XL];
+    __shared__ float4 lf[NBUF][XL];
+    __shared__ float ku[XCH ? 3 * NDIR * CL : 1];
     const int tid = threadIdx.x;
     const SimConst c = A.c;
     const bool ground = c.ground != 0;
@@ -52,9 +60,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         const int pbase = NDIR * base;
         const size_t rbase = (size_t)A.n_steps * base;
         const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f), zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (XCH)
+            for (int i = tid; i < 3 * NDIR * CL; i += BS) ku[i] = 0.f;
         for (int i = tid; i < PAD; i += BS) {
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < NBUF; ++b) {
                 xs[b][i] = ghost;
                 xs[b][PAD + SL + i] = ghost;
                 lf[b][i] = zero;
@@ -65,7 +75,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         bool pres[NPT];
         float3 X0[NPT], lx[NPT], lv[NPT];
         float pk[NPT][NDIR], pa[NPT][NDIR], pb[NPT][NDIR], pik[NPT][NDIR];
-        float qk[NPT][NDIR], qa[NPT][NDIR], qb[NPT][NDIR];
+        float qk[NPT][NQ], qa[NPT][NQ], qb[NPT][NQ];
         float gk[NPT][NDIR], gs[NPT][NDIR], gc[NPT][NDIR];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
@@ -89,18 +99,24 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 gk[k][d] = live ? A.gk[pi] : 0.f;
                 gs[k][d] = live ? A.gs[pi] : 0.f;
                 gc[k][d] = live ? A.gc[pi] : 0.f;
-                const int lo = s - dir_off(d, N);
-                const bool ok = live && lo >= 0;
-                const int qi = pbase + d * SL + (ok ? lo : 0);
-                qk[k][d] = ok ? A.pl.k[qi] : 0.f;
-                qa[k][d] = ok ? A.pl.kal[qi] : 0.f;
-                qb[k][d] = (ok && PHASE) ? A.pl.kbe[qi] : 0.f;
+            }
+            if (!XCH) {
+#pragma unroll
+                for (int d = 0; d < NQ; ++d) {
+                    const int lo = s - dir_off(d, N);
+                    const bool ok = live && lo >= 0;
+                    const int qi = pbase + d * SL + (ok ? lo : 0);
+                    qk[k][d] = ok ? A.pl.k[qi] : 0.f;
+                    qa[k][d] = ok ? A.pl.kal[qi] : 0.f;
+                    qb[k][d] = (ok && PHASE) ? A.pl.kbe[qi] : 0.f;
+                }
             }
         }
         __syncthreads();
 
         for (int t = A.n_steps - 1; t >= 0; --t) {
-            const int b = t & 1;
+            const int b = XCH ? 0 : (t & 1);
+            if (XCH) __syncthreads();  // the previous step's readers are done with the buffers
             const float2 sct = A.sc[t];
             float3 Xr[NPT], LF[NPT];
             // node-local part of the reverse step
@@ -145,8 +161,10 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
             }
             __syncthreads();
             // spring part: every node takes K_s (lF_hi - lF_lo) from each spring it touches
+            float3 accs[NPT];
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
+                accs[k] = make_float3(0.f, 0.f, 0.f);
                 const int s = tid + k * BS;
                 if (s >= SL || !pres[k]) continue;
                 const float4 *xsb = xs[b] + s;
@@ -166,33 +184,65 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     const float c1 = fmaf(-kL, ir, pk[k][d]);
                     const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
                     const float c2 = (kL * ir) * ir * ir * du;
-                    acc.x += fmaf(c1, ux, c2 * dx);
-                    acc.y += fmaf(c1, uy, c2 * dy);
-                    acc.z += fmaf(c1, uz, c2 * dz);
+                    const float kx = fmaf(c1, ux, c2 * dx), ky = fmaf(c1, uy, c2 * dy), kz = fmaf(c1, uz, c2 * dz);
+                    acc.x += kx;
+                    acc.y += ky;
+                    acc.z += kz;
+                    if (XCH) {
+                        ku[(0 * NDIR + d) * CL + PAD + s] = kx;
+                        ku[(1 * NDIR + d) * CL + PAD + s] = ky;
+                        ku[(2 * NDIR + d) * CL + PAD + s] = kz;
+                    }
                     const float dhu = du * ir;
                     gk[k][d] = fmaf(-(r2 * ir - kL * pik[k][d]), dhu, gk[k][d]);
                     const float gL = pk[k][d] * dhu;
                     gs[k][d] = fmaf(gL, sct.x, gs[k][d]);
                     gc[k][d] = fmaf(gL, sct.y, gc[k][d]);
                 }
+                if (!XCH) {
 #pragma unroll
-                for (int d = 0; d < NDIR; ++d) {
-                    // backward spring: self is the upper end
-                    const float3 Y = ld3(xsb + (PAD - dir_off(d, N)));
-                    const float3 LI = ld3(lfb + (PAD - dir_off(d, N)));
-                    const float dx = Xr[k].x - Y.x, dy = Xr[k].y - Y.y, dz = Xr[k].z - Y.z;
-                    const float ux = LF[k].x - LI.x, uy = LF[k].y - LI.y, uz = LF[k].z - LI.z;
-                    const float r2 = len2(dx, dy, dz);
-                    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
-                    float kL = fmaf(qa[k][d], sct.x, qk[k][d] * L0d(c, d));
-                    if (PHASE) kL = fmaf(qb[k][d], sct.y, kL);
-                    const float c1 = fmaf(-kL, ir, qk[k][d]);
-                    const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
-                    const float c2 = (kL * ir) * ir * ir * du;
-                    acc.x -= fmaf(c1, ux, c2 * dx);
-                    acc.y -= fmaf(c1, uy, c2 * dy);
-                    acc.z -= fmaf(c1, uz, c2 * dz);
+                    for (int d = 0; d < NQ; ++d) {
+                        // backward spring: self is the upper end
+                        const float3 Y = ld3(xsb + (PAD - dir_off(d, N)));
+                        const float3 LI = ld3(lfb + (PAD - dir_off(d, N)));
+                        const float dx = Xr[k].x - Y.x, dy = Xr[k].y - Y.y, dz = Xr[k].z - Y.z;
+                        const float ux = LF[k].x - LI.x, uy = LF[k].y - LI.y, uz = LF[k].z - LI.z;
+                        const float r2 = len2(dx, dy, dz);
+                        const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+                        float kL = fmaf(qa[k][d], sct.x, qk[k][d] * L0d(c, d));
+                        if (PHASE) kL = fmaf(qb[k][d], sct.y, kL);
+                        const float c1 = fmaf(-kL, ir, qk[k][d]);
+                        const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+                        const float c2 = (kL * ir) * ir * ir * du;
+                        acc.x -= fmaf(c1, ux, c2 * dx);
+                        acc.y -= fmaf(c1, uy, c2 * dy);
+                        acc.z -= fmaf(c1, uz, c2 * dz);
+                    }
                 }
+                accs[k] = acc;
+            }
+            if (XCH) {
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < NPT; ++k) {
+                    const int s = tid + k * BS;
+                    if (s >= SL || !pres[k]) continue;
+                    float3 acc = accs[k];
+#pragma unroll
+                    for (int d = 0; d < NDIR; ++d) {
+                        const int lo = PAD + s - dir_off(d, N);
+                        acc.x -= ku[(0 * NDIR + d) * CL + lo];
+                        acc.y -= ku[(1 * NDIR + d) * CL + lo];
+                        acc.z -= ku[(2 * NDIR + d) * CL + lo];
+                    }
+                    accs[k] = acc;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int s = tid + k * BS;
+                if (s >= SL || !pres[k]) continue;
+                const float3 acc = accs[k];
                 lx[k].x += acc.x;
                 lx[k].y += acc.y;
                 lx[k].z += acc.z;
@@ -474,11 +524,11 @@ struct AdjEntry {
     int n, block;
     AdjFn fn, fn_phase;
 };
-#define SR_AE(NN, BS) \
-    { NN, BS, k_adjoint<NN + 1, BS, false>, k_adjoint<NN + 1, BS, true> }
-const AdjEntry kAdj[] = {SR_AE(1, 64),   SR_AE(2, 64),   SR_AE(3, 64),    SR_AE(4, 128),
-                         SR_AE(5, 256),  SR_AE(6, 384),  SR_AE(7, 512),   SR_AE(8, 768),
-                         SR_AE(9, 1024), SR_AE(10, 704), SR_AE(11, 1024)};
+#define SR_AE(NN, BS, X) \
+    { NN, BS, k_adjoint<NN + 1, BS, false, X>, k_adjoint<NN + 1, BS, true, X> }
+const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AE(4, 128, true),
+                         SR_AE(5, 256, true),   SR_AE(6, 384, true),   SR_AE(7, 512, true),  SR_AE(8, 768, true),
+                         SR_AE(9, 1024, false), SR_AE(10, 704, false), SR_AE(11, 1024, false)};
 
 }  // namespace
 

@@ -84,6 +84,8 @@ hipError_t launch_query(const RobotInfo *robots, int R, int max_side, const floa
 hipError_t launch_ga(const float *fit, const float *gin, float *gout, int P, int L, int E, int k, uint64_t pc,
                      uint64_t pm, float sigma, uint64_t seed, uint64_t gen, int32_t *dec, hipStream_t st);
 
+hipError_t launch_micro(int which, int iters, int grid, float *out, hipStream_t st, double *units);
+
 hipError_t launch_sincos(float2 *sc, const int64_t *d_step, int n, double omega_dt, int on, hipStream_t st);
 hipError_t launch_sincos_at(float2 *sc, int64_t step0, int n, double omega_dt, int on, hipStream_t st);
 

@@ -204,6 +204,37 @@ const char *sr_last_error(void) { return g_err.c_str(); }
 
 int sr_version(void) { return 1; }
 
+int sr_microbench(int32_t which, int32_t iters, double *seconds, double *units) {
+    if (which < 0 || which > 4 || iters < 1 || !seconds || !units) return set_err(SR_EINVAL, "bad microbenchmark request");
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int grid = (cus > 0 ? cus : 256) * 8;
+    float *out = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&out, sizeof(float) * grid * 256);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double u = 0.0;
+    if (e == hipSuccess) e = launch_micro(which, iters, grid, out, st, &u);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = launch_micro(which, iters, grid, out, st, &u);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    if (out) (void)hipFree(out);
+    if (e != hipSuccess) return set_err(SR_EHIP, "microbenchmark: %s", hipGetErrorString(e));
+    *seconds = ms * 1e-3;
+    *units = u;
+    return SR_OK;
+}
+
 int sr_persist_configs(int32_t n, int32_t *blocks, int32_t *variants, int32_t cap) {
     if (n < 1 || n > SR_MAX_SIDE) return set_err(SR_EINVAL, "side %d outside 1..%d", n, SR_MAX_SIDE);
     return persist_list(n, blocks, variants, cap < 0 ? 0 : cap);

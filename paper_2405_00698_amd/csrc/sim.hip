@@ -485,14 +485,16 @@ struct PersistEntry {
 
 // The first entry of each side is its default configuration.
 const PersistEntry kPersist[] = {
-    SR_PE(1, 64, 1, 0),   SR_PE(2, 64, 1, 0),   SR_PE(3, 64, 1, 0),    SR_PE(4, 128, 1, 0),  SR_PE(4, 64, 1, 0),
-    SR_PE(5, 256, 1, 0),  SR_PE(5, 128, 1, 0),  SR_PE(6, 384, 1, 0),   SR_PE(6, 192, 1, 0),  SR_PE(7, 512, 1, 0),
-    SR_PE(7, 256, 1, 0),  SR_PE(8, 768, 1, 0),  SR_PE(8, 384, 1, 0),   SR_PE(8, 256, 1, 0),  SR_PE(8, 768, 0, 0),
-    SR_PE(8, 384, 1, 1),  SR_PE(8, 256, 1, 1),  SR_PE(9, 1024, 1, 0),  SR_PE(9, 512, 1, 0),  SR_PE(9, 512, 1, 1),
-    SR_PE(10, 448, 1, 0), SR_PE(10, 448, 1, 1), SR_PE(10, 704, 1, 0),  SR_PE(10, 704, 1, 1), SR_PE(10, 1024, 1, 0),
-    SR_PE(10, 1024, 1, 1), SR_PE(10, 704, 0, 0), SR_PE(10, 704, 2, 0), SR_PE(10, 448, 2, 0), SR_PE(10, 448, 0, 0),
-    SR_PE(11, 896, 1, 0), SR_PE(11, 896, 1, 1), SR_PE(11, 576, 1, 0),  SR_PE(11, 576, 1, 1), SR_PE(12, 768, 2, 0),
-    SR_PE(12, 768, 2, 1), SR_PE(12, 768, 0, 0), SR_PE(12, 1024, 2, 0), SR_PE(12, 1024, 2, 1),
+    SR_PE(1, 64, 1, 0),    SR_PE(2, 64, 1, 0),    SR_PE(3, 64, 1, 0),    SR_PE(4, 128, 1, 0),  SR_PE(4, 64, 1, 0),
+    SR_PE(4, 128, 0, 0),   SR_PE(5, 256, 1, 0),   SR_PE(5, 128, 1, 0),   SR_PE(5, 256, 0, 0),  SR_PE(6, 384, 1, 0),
+    SR_PE(6, 192, 1, 0),   SR_PE(6, 384, 0, 0),   SR_PE(7, 512, 1, 0),   SR_PE(7, 256, 1, 0),  SR_PE(7, 512, 0, 0),
+    SR_PE(8, 768, 0, 0),   SR_PE(8, 768, 1, 0),   SR_PE(8, 384, 1, 0),   SR_PE(8, 256, 1, 0),  SR_PE(8, 384, 1, 1),
+    SR_PE(8, 256, 1, 1),   SR_PE(8, 512, 0, 0),   SR_PE(8, 256, 0, 0),   SR_PE(9, 1024, 1, 0), SR_PE(9, 512, 1, 0),
+    SR_PE(9, 512, 1, 1),   SR_PE(9, 1024, 0, 0),  SR_PE(9, 512, 0, 0),   SR_PE(10, 512, 1, 0), SR_PE(10, 448, 1, 0),
+    SR_PE(10, 448, 1, 1),  SR_PE(10, 704, 1, 0),  SR_PE(10, 1024, 1, 0), SR_PE(10, 704, 0, 0), SR_PE(10, 704, 2, 0),
+    SR_PE(10, 448, 2, 0),  SR_PE(10, 448, 0, 0),  SR_PE(10, 512, 0, 0),  SR_PE(10, 384, 1, 0), SR_PE(11, 896, 1, 0),
+    SR_PE(11, 896, 1, 1),  SR_PE(11, 576, 1, 0),  SR_PE(11, 576, 1, 1),  SR_PE(11, 1024, 0, 0), SR_PE(12, 768, 2, 0),
+    SR_PE(12, 768, 2, 1),  SR_PE(12, 768, 0, 0),  SR_PE(12, 1024, 2, 0), SR_PE(12, 1024, 2, 1),
 };
 
 #define SR_REC(NN, BS, VAR) \

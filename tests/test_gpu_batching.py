@@ -77,3 +77,10 @@ def test_uneven_codesign_loop_is_reproducible():
         assert np.all(np.isfinite(fits[-1]))
     assert np.array_equal(finals[0][0], finals[1][0])
     assert np.array_equal(finals[0][1], finals[1][1])
+
+
+def test_microbenchmarks_report_positive_rates():
+    from paper_2405_00698_amd import api
+    rates = {k: api.microbench(k, iters=256) for k in api.MICRO}
+    say("microbenchmarks", {k: "%.3g" % v for k, v in rates.items()})
+    assert all(v > 0 for v in rates.values())

@@ -107,8 +107,8 @@ def test_plain_and_persistent_agree_bitwise():
 
 
 @pytest.mark.parametrize("n,configs", [(8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5)]),
-                                       (10, [(448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
-                                             (448, 0), (448, 5), (704, 5), (1024, 5)]),
+                                       (10, [(512, 1), (448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
+                                             (448, 0), (448, 5), (512, 0), (384, 1)]),
                                        (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6)])])
 def test_persistent_variants_bitwise(n, configs):
     sides = [n] * 4
