@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--robots", type=int, default=4096)
     ap.add_argument("--side", type=int, default=10)
+    ap.add_argument("--workload", default="uniform", choices=["uniform", "uneven"],
+                    help="uniform: all robots of --side; uneven: sides drawn uniformly from 4..12 and "
+                         "empty-class biases U(-0.2, 0.4), only the largest component kept")
     ap.add_argument("--sim-steps", type=int, default=10000)
     ap.add_argument("--mode", default="persistent", choices=["persistent", "plain"])
     ap.add_argument("--query", default="fp32", choices=["bf16", "fp32"])
@@ -63,6 +66,7 @@ def parse():
     ap.add_argument("--cpu-robots", type=int, default=64)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-step-launch baseline and the adjoint/forward ratio")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default step-kernel configuration")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (HBM counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -89,7 +93,7 @@ def plain_baseline(api, inputs, torch, R, n, steps, prec):
     """The same workload stepped by the per-step-launch kernel (state in HBM)."""
     from paper_2405_00698_amd import SR_STEP_PLAIN
     dev = torch.device("cuda:0")
-    P = api.Population([n] * R)
+    P = api.Population(sides)
     P.set_step_config(SR_STEP_PLAIN)
     P.build_from_genomes(torch.from_numpy(inputs.random_genomes(R)).to(dev),
                          torch.from_numpy(inputs.gaussian_B()).to(dev), prec)
@@ -146,17 +150,29 @@ def main():
     torch.cuda.set_device(dev)
     R, n = args.robots, args.side
     B = inputs.gaussian_B()
-    G = inputs.random_genomes(R)
+    if args.workload == "uneven":
+        sides = [int(q) for q in inputs.grid_sides(R, 4, 12)]
+        G = inputs.random_genomes(R, empty_bias=inputs.uniform(R, -0.2, 0.4, seed=2))
+    else:
+        sides = [n] * R
+        G = inputs.random_genomes(R)
     Bt = torch.from_numpy(B).to(dev)
     Gt = [torch.from_numpy(G).to(dev), torch.empty((R, _lib.GENOME_LEN), dtype=torch.float32, device=dev)]
     fit = torch.empty(R, dtype=torch.float32, device=dev)
-    P = api.Population([n] * R)
+    P = api.Population(sides)
     P.set_step_config(SR_STEP_PLAIN if args.mode == "plain" else SR_STEP_AUTO)
     prec = SR_QUERY_BF16 if args.query == "bf16" else SR_QUERY_FP32
     has_ga = hasattr(_lib.load(), "ga_generation")
     if has_ga:
         from paper_2405_00698_amd.api import ga_generation, GAConfig
         gacfg = GAConfig()
+
+    tuned = None
+    if not args.no_tune:
+        # pick the fastest compiled step-kernel configuration for this population (cached)
+        from paper_2405_00698_amd import tune
+        P.build_from_genomes(Gt[0], Bt, prec)
+        tuned = {int(k): list(v) for k, v in tune.tune(P, steps=200, cache_path="/tmp/softrobot_tune.json").items()}
 
     stream = torch.cuda.current_stream()
     springs_per_gen = []
@@ -210,17 +226,19 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic: seeded random genomes (W ~ N(0, 1/64), b = 0), B ~ N(0, 1)",
-        "config": {"workload": "%d robots on %d^3 voxel grids, %d sim steps per generation (dt 1e-4 s), "
-                               "%s genome query, GA %s" % (R, n, args.sim_steps, args.query,
-                                                            "on" if has_ga else "off"),
+        "config": {"workload": ("%d robots on %d^3 voxel grids" % (R, n) if args.workload == "uniform" else
+                                "%d robots with sides uniform on 4..12" % R) +
+                               ", %d sim steps per generation (dt 1e-4 s), %s genome query, GA %s"
+                               % (args.sim_steps, args.query, "on" if has_ga else "off"),
                    "robots": R, "grid_side": n, "sim_steps": args.sim_steps, "mode": args.mode,
-                   "springs_per_generation": springs_per_gen[0][0], "masses_per_generation": springs_per_gen[0][1]},
+                   "springs_per_generation": springs_per_gen[0][0], "masses_per_generation": springs_per_gen[0][1],
+                   "step_kernel": {q: P.kernel_config(q) for q in sorted(set(sides))}, "tuned": tuned},
         "sim_kernel_s": kern_s,
         "sim_spring_updates_per_s": su_per_launch / kern_s,
         "roofline": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
                      "frac": lds_gbs / LDS_PEAK_GBS,
-                     "traffic": measured_traffic(P.kernel_config(n), args.sim_steps) if args.mode == "persistent"
-                     else None},
+                     "traffic": measured_traffic(P.kernel_config(n), args.sim_steps)
+                     if args.mode == "persistent" and args.workload == "uniform" else None},
         "roofline_alu": {"bound": "alu", "achieved": valu / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                          "unit": "T lane-op slots/s", "frac": valu / VALU_PEAK_SLOTS},
     }
@@ -230,7 +248,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * src.numel() * 4
-    if not args.no_extras:
+    if not args.no_extras and args.workload == "uniform":
         peaks = {name: api.microbench(name) for name in ("lds_read_16B", "lds_read_12B", "lds_read_4B",
                                                          "valu_fma", "valu_rsq")}
         out["measured_peaks"] = {k: (v / 1e9 if k.startswith("lds") else v / 1e12) for k, v in peaks.items()}
@@ -242,7 +260,7 @@ def main():
         out["per_step_launch_spring_updates_per_s"] = pl
         out["persistent_over_per_step_launch"] = (su_per_launch / kern_s) / pl
         out["adjoint_forward_ratio"] = adjoint_ratio(api, inputs, torch)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "uniform":
         out["cpu_baseline"] = cpu_baseline(args, G, B)
     print(json.dumps(out), flush=True)
 

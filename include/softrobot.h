@@ -154,7 +154,8 @@ int pop_set_graphs(sr_pop *pop, int32_t enable);
 /* Picks the persistent kernel for robots of side n: block threads per
  * workgroup and variant (0 recompute every spring force at both ends,
  * 1 exchange spring coefficients through LDS, 2 exchange in two direction
- * chunks; +4 bounds the LDS loads in flight to save registers).  All variants
+ * chunks; +4 bounds the LDS loads in flight to save registers; +8 reads
+ * positions with 12-byte instead of 16-byte LDS loads).  All variants
  * give bit-identical results.  SR_EUNSUPPORTED for a combination the library
  * lacks. */
 int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t variant);
@@ -197,7 +198,8 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
                  const float *genomes, const float *B, float *g_genome);
 
 /* fitness (dev, [n_robots] float): mean over nodes of x_x(now) - x_x(build),
- * i.e. the centre-of-mass displacement along +x; -inf for a diverged robot. */
+ * i.e. the centre-of-mass displacement along +x; -inf for a diverged robot
+ * and for a robot with no occupied voxel (it has no body). */
 int pop_fitness(sr_pop *pop, float *fitness);
 
 /* Introspection (host outputs; synchronise the stream).  Any pointer may be

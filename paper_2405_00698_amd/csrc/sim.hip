@@ -160,7 +160,7 @@ constexpr size_t lds_bytes() {
     return 2 * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL;
 }
 
-template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false>
+template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
@@ -254,7 +254,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     if (s < SL) {
 #pragma unroll
                         for (int d = 0; d < NDIR; ++d) {
-                            const float3 Y = ld3(xc + s + (PAD + dir_off(d, N)));
+                            const float3 Y = ldx<WIDE>(xc + s + (PAD + dir_off(d, N)));
                             const float dx = Y.x - xr[k].x, dy = Y.y - xr[k].y, dz = Y.z - xr[k].z;
                             const float cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
                                                                 PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz));
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         }
 #pragma unroll
                         for (int d = 0; d < NQ; ++d) {
-                            const float3 Y = ld3(xc + s + (PAD - dir_off(d, N)));
+                            const float3 Y = ldx<WIDE>(xc + s + (PAD - dir_off(d, N)));
                             const float ex = Y.x - xr[k].x, ey = Y.y - xr[k].y, ez = Y.z - xr[k].z;
                             const float cf = spring_coef<PHASE>(qk[k][d], qk[k][d] * L0d(c, d), qa[k][d], qb[k][d],
                                                                 sct.x, sct.y, len2(ex, ey, ez));
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             float *cs = coef + s;
                             float3 Y[NDIR];
 #pragma unroll
-                            for (int d = d0; d < d1; ++d) Y[d] = ld3(xs + (PAD + dir_off(d, N)));
+                            for (int d = d0; d < d1; ++d) Y[d] = ldx<WIDE>(xs + (PAD + dir_off(d, N)));
                             float cfv[NDIR];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             float cfv[NDIR];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
-                                Y[d] = ld3(xs + (PAD - dir_off(d, N)));
+                                Y[d] = ldx<WIDE>(xs + (PAD - dir_off(d, N)));
                                 cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
                             }
 #pragma unroll
@@ -382,7 +382,8 @@ __global__ __launch_bounds__(256) void k_fitness(const RobotInfo *robots, const 
     __syncthreads();
     if (threadIdx.x == 0) {
         const float tot = (part[0] + part[1]) + (part[2] + part[3]);
-        float f = ri.M > 0 ? tot / (float)ri.M : 0.f;
+        // a robot with no kept voxel has no body to move: worst fitness
+        float f = ri.M > 0 ? tot / (float)ri.M : -INFINITY;
         if (diverged[blockIdx.x] || !(fabsf(f) <= 3.0e38f)) f = -INFINITY;
         fit[blockIdx.x] = f;
     }
@@ -476,25 +477,25 @@ struct PersistEntry {
 };
 
 // variant code: exchange variant (0, 1, 2) + 4 when scheduling fences bound the
-// number of LDS loads in flight (fewer registers, less latency hiding)
-#define SR_PE(NN, BS, VAR, F)                                                                     \
-    {                                                                                             \
-        NN, BS, VAR + 4 * F, k_persist<NN + 1, BS, VAR, F, false>, k_persist<NN + 1, BS, VAR, F, true>, \
-            lds_bytes<NN + 1, BS, VAR>()                                                          \
+// number of LDS loads in flight + 8 for 12-byte instead of 16-byte position loads
+#define SR_PE(NN, BS, VAR, F, W)                                                                        \
+    {                                                                                                   \
+        NN, BS, VAR + 4 * F + 8 * (1 - W), k_persist<NN + 1, BS, VAR, F, false, false, W>,              \
+            k_persist<NN + 1, BS, VAR, F, true, false, W>, lds_bytes<NN + 1, BS, VAR>()                 \
     }
 
 // The first entry of each side is its default configuration.
 const PersistEntry kPersist[] = {
-    SR_PE(1, 64, 1, 0),    SR_PE(2, 64, 1, 0),    SR_PE(3, 64, 1, 0),    SR_PE(4, 128, 1, 0),  SR_PE(4, 64, 1, 0),
-    SR_PE(4, 128, 0, 0),   SR_PE(5, 256, 1, 0),   SR_PE(5, 128, 1, 0),   SR_PE(5, 256, 0, 0),  SR_PE(6, 384, 1, 0),
-    SR_PE(6, 192, 1, 0),   SR_PE(6, 384, 0, 0),   SR_PE(7, 512, 1, 0),   SR_PE(7, 256, 1, 0),  SR_PE(7, 512, 0, 0),
-    SR_PE(8, 768, 0, 0),   SR_PE(8, 768, 1, 0),   SR_PE(8, 384, 1, 0),   SR_PE(8, 256, 1, 0),  SR_PE(8, 384, 1, 1),
-    SR_PE(8, 256, 1, 1),   SR_PE(8, 512, 0, 0),   SR_PE(8, 256, 0, 0),   SR_PE(9, 1024, 1, 0), SR_PE(9, 512, 1, 0),
-    SR_PE(9, 512, 1, 1),   SR_PE(9, 1024, 0, 0),  SR_PE(9, 512, 0, 0),   SR_PE(10, 512, 1, 0), SR_PE(10, 448, 1, 0),
-    SR_PE(10, 448, 1, 1),  SR_PE(10, 704, 1, 0),  SR_PE(10, 1024, 1, 0), SR_PE(10, 704, 0, 0), SR_PE(10, 704, 2, 0),
-    SR_PE(10, 448, 2, 0),  SR_PE(10, 448, 0, 0),  SR_PE(10, 512, 0, 0),  SR_PE(10, 384, 1, 0), SR_PE(11, 896, 1, 0),
-    SR_PE(11, 896, 1, 1),  SR_PE(11, 576, 1, 0),  SR_PE(11, 576, 1, 1),  SR_PE(11, 1024, 0, 0), SR_PE(12, 768, 2, 0),
-    SR_PE(12, 768, 2, 1),  SR_PE(12, 768, 0, 0),  SR_PE(12, 1024, 2, 0), SR_PE(12, 1024, 2, 1),
+    SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
+    SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
+    SR_PE(6, 192, 1, 0, 1),   SR_PE(6, 384, 0, 0, 1),   SR_PE(7, 512, 1, 0, 1),   SR_PE(7, 256, 1, 0, 1),  SR_PE(7, 512, 0, 0, 1),
+    SR_PE(8, 768, 0, 0, 0), SR_PE(8, 768, 0, 0, 1), SR_PE(8, 768, 1, 0, 0),   SR_PE(8, 768, 1, 0, 1),   SR_PE(8, 384, 1, 0, 1),   SR_PE(8, 256, 1, 0, 1),  SR_PE(8, 384, 1, 1, 1),
+    SR_PE(8, 256, 1, 1, 1),   SR_PE(8, 512, 0, 0, 1),   SR_PE(8, 256, 0, 0, 1),   SR_PE(9, 1024, 1, 0, 1), SR_PE(9, 512, 1, 0, 1),
+    SR_PE(9, 512, 1, 1, 1),   SR_PE(9, 1024, 0, 0, 1),  SR_PE(9, 512, 0, 0, 1),   SR_PE(10, 512, 1, 0, 1), SR_PE(10, 448, 1, 0, 1),
+    SR_PE(10, 448, 1, 1, 1),  SR_PE(10, 704, 1, 0, 1),  SR_PE(10, 1024, 1, 0, 1), SR_PE(10, 704, 0, 0, 1), SR_PE(10, 704, 2, 0, 1),
+    SR_PE(10, 448, 2, 0, 1),  SR_PE(10, 448, 0, 0, 1),  SR_PE(10, 512, 0, 0, 1),  SR_PE(10, 384, 1, 0, 1), SR_PE(11, 896, 1, 0, 1),
+    SR_PE(11, 896, 1, 1, 1),  SR_PE(11, 576, 1, 0, 1),  SR_PE(11, 576, 1, 1, 1),  SR_PE(11, 1024, 0, 0, 1), SR_PE(12, 768, 2, 0, 1),
+    SR_PE(12, 768, 2, 1, 1),  SR_PE(12, 768, 0, 0, 1),  SR_PE(12, 1024, 2, 0, 1), SR_PE(12, 1024, 2, 1, 1),
 };
 
 #define SR_REC(NN, BS, VAR) \

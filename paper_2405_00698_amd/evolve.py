@@ -1,0 +1,116 @@
+"""Co-design loop driver (Sec. II-C, Table I): each generation builds every
+robot from its genome (Eq. (1) encoding, MLP, heads), simulates it, scores
+it, and breeds the next genomes on the device.
+
+The paper steers the GA with an LLM that reads the parameters and the
+population of the previous three generations and proposes new parameters
+(Sec. II-D).  Here that role is a plain callback, `supervisor(history) ->
+GAConfig`, called once per generation with the last three generations'
+parameters and statistics; `rule_supervisor` is a deterministic stand-in.
+Every step of the hot path runs in the HIP library; this module only
+sequences the calls and logs per-generation statistics (fitness min / mean /
+max and a diversity measure) on the host.
+"""
+import json
+import time
+
+import numpy as np
+import torch
+
+from . import SR_QUERY_BF16, inputs
+from .api import GAConfig, Population, ga_generation
+
+
+def diversity(kept_cls, sides, genomes):
+    """Mean pairwise Hamming distance between the robots' kept-class grids
+    (robots of equal side only; a class differs or a voxel is kept in one and
+    not the other), and the mean pairwise L2 distance between genomes."""
+    out_h, pairs = 0.0, 0
+    offs = np.concatenate([[0], np.cumsum([n ** 3 for n in sides])])
+    by_side = {}
+    for r, n in enumerate(sides):
+        by_side.setdefault(n, []).append(kept_cls[offs[r]:offs[r + 1]])
+    for n, grids in by_side.items():
+        g = np.stack(grids)
+        for i in range(len(g)):
+            d = (g[i + 1:] != g[i]).mean(axis=1)
+            out_h += d.sum()
+            pairs += len(d)
+    G = genomes.astype(np.float64)
+    sq = (G * G).sum(1)
+    d2 = np.maximum(sq[:, None] + sq[None, :] - 2 * G @ G.T, 0.0)
+    iu = np.triu_indices(len(G), 1)
+    return (out_h / pairs if pairs else 0.0), float(np.sqrt(d2[iu]).mean()) if len(iu[0]) else 0.0
+
+
+def rule_supervisor(history):
+    """Deterministic stand-in for the LLM supervisor: when the best fitness
+    stalls for the last three generations or the morphology diversity falls,
+    raise the mutation rate and scale; otherwise relax them towards Table I."""
+    cur = history[-1]["params"]
+    rate, sigma = cur["p_mut"], cur["sigma"]
+    if len(history) >= 3:
+        best = [h["fit_max"] for h in history[-3:]]
+        div = [h["div_morph"] for h in history[-3:]]
+        if best[-1] <= best[0] or div[-1] < 0.5 * div[0]:
+            rate, sigma = min(0.3, rate * 1.5), min(0.1, sigma * 1.5)
+        else:
+            rate, sigma = max(0.1, rate * 0.9), max(0.02, sigma * 0.9)
+    return dict(cur, p_mut=rate, sigma=sigma)
+
+
+def evolve(sides, generations=100, sim_steps=10000, seed_genome=1, seed_ga=3, sigma_B=1.0,
+           params=None, supervisor=None, empty_bias=None, log=None, precision=SR_QUERY_BF16, **sim):
+    """Runs `generations` generations on the given grid sides; returns the
+    per-generation history (parameters, fitness statistics, diversity, times)."""
+    dev = torch.device("cuda:0")
+    R = len(sides)
+    params = dict(elite_frac=0.3, tournament_k=4, p_cross=0.4, p_mut=0.1, sigma=0.02) if params is None else params
+    B = torch.from_numpy(inputs.gaussian_B(sigma=sigma_B)).to(dev)
+    G = [torch.from_numpy(inputs.random_genomes(R, seed=seed_genome, empty_bias=empty_bias)).to(dev),
+         torch.empty((R, inputs.GENOME_LEN), dtype=torch.float32, device=dev)]
+    P = Population(sides, **sim)
+    fit = torch.empty(R, dtype=torch.float32, device=dev)
+    history = []
+    for g in range(generations):
+        t0 = time.perf_counter()
+        cur, nxt = G[g % 2], G[(g + 1) % 2]
+        P.build_from_genomes(cur, B, precision)
+        P.step(sim_steps)
+        P.fitness(fit)
+        f = fit.cpu().numpy()
+        kept = P.voxels()[0].cpu().numpy()
+        dm, dg = diversity(kept, sides, cur.cpu().numpy())
+        finite = f[np.isfinite(f)]
+        rec = {"generation": g, "params": dict(params),
+               "fit_max": float(finite.max()) if len(finite) else float("-inf"),
+               "fit_mean": float(finite.mean()) if len(finite) else float("-inf"),
+               "fit_min": float(finite.min()) if len(finite) else float("-inf"),
+               "diverged": int((~np.isfinite(f)).sum()), "div_morph": dm, "div_genome": dg}
+        history.append(rec)
+        if supervisor is not None:
+            params = supervisor(history[-3:])
+        ga_generation(fit, cur, nxt, GAConfig(**params), seed=seed_ga, generation=g)
+        torch.cuda.synchronize()
+        rec["seconds"] = time.perf_counter() - t0
+        if log is not None:
+            log.write(json.dumps(rec) + "\n")
+            log.flush()
+    P.close()
+    return history
+
+
+if __name__ == "__main__":
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="co-design loop: the paper's shape is 30 robots of 5^3, 100 generations")
+    ap.add_argument("--robots", type=int, default=30)
+    ap.add_argument("--side", type=int, default=5)
+    ap.add_argument("--generations", type=int, default=100)
+    ap.add_argument("--sim-steps", type=int, default=10000)
+    ap.add_argument("--sigma-B", type=float, default=1.0, help="standard deviation of the encoding matrix B")
+    ap.add_argument("--supervisor", action="store_true", help="use the rule-based stand-in for the LLM supervisor")
+    ap.add_argument("--seed", type=int, default=1)
+    a = ap.parse_args()
+    evolve([a.side] * a.robots, a.generations, a.sim_steps, seed_genome=a.seed, sigma_B=a.sigma_B,
+           supervisor=rule_supervisor if a.supervisor else None, log=sys.stdout)

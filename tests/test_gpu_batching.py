@@ -84,3 +84,17 @@ def test_microbenchmarks_report_positive_rates():
     rates = {k: api.microbench(k, iters=256) for k in api.MICRO}
     say("microbenchmarks", {k: "%.3g" % v for k, v in rates.items()})
     assert all(v > 0 for v in rates.values())
+
+
+def test_codesign_driver_paper_shape_short():
+    """The paper's experiment shape (30 robots of 5^3, Table I rates), 4
+    generations of 2000 steps with the supervisor stand-in: statistics logged,
+    best fitness never lost (elites are re-simulated at their slot's side,
+    equal here), reproducible."""
+    from paper_2405_00698_amd.evolve import evolve, rule_supervisor
+    h1 = evolve([5] * 30, generations=4, sim_steps=2000, supervisor=rule_supervisor)
+    h2 = evolve([5] * 30, generations=4, sim_steps=2000, supervisor=rule_supervisor)
+    assert [r["fit_max"] for r in h1] == [r["fit_max"] for r in h2]
+    best = [r["fit_max"] for r in h1]
+    assert all(b2 >= b1 for b1, b2 in zip(best, best[1:]))
+    say("paper-shape run", [("%.4f" % r["fit_max"], "%.3f" % r["div_morph"]) for r in h1])

@@ -106,7 +106,7 @@ def test_plain_and_persistent_agree_bitwise():
     assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
 
 
-@pytest.mark.parametrize("n,configs", [(8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5)]),
+@pytest.mark.parametrize("n,configs", [(8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9)]),
                                        (10, [(512, 1), (448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
                                              (448, 0), (448, 5), (512, 0), (384, 1)]),
                                        (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6)])])
@@ -196,3 +196,29 @@ def test_full_size_sampled_parity(orc, R, n):
         Rb = orc.Robot(n, cls[r * nv:(r + 1) * nv], w[r * nv:(r + 1) * nv].astype(np.float64))
         Rb.step(200)
         assert rel_err(xs[r], Rb.state()[0]) <= 1e-3, r
+
+
+def test_empty_and_single_voxel_robots(orc):
+    """Edge cases: a robot whose voxels are all empty (no body: no nodes, no
+    springs, fitness -inf), single-voxel robots of every side, a lone robot."""
+    sides = [3, 1, 5, 12]
+    cls, w = voxel_population(sides, 71, p_empty=0.3)
+    cls[:27] = 0                                  # robot 0 empty
+    cls[27] = 2                                   # robot 1: one contracting voxel
+    P = gpu_population(sides, cls, w)
+    M, S, mo, so = P.counts()
+    assert (M[0], S[0]) == (0, 0) and (M[1], S[1]) == (8, 28)
+    P.step(300)
+    fit = P.fitness().cpu().numpy()
+    assert fit[0] == -np.inf and np.all(np.isfinite(fit[1:]))
+    xs, _, _ = gpu_states(P)
+    for r in (1, 2, 3):
+        o = sum(n ** 3 for n in sides[:r])
+        R = orc.Robot(sides[r], cls[o:o + sides[r] ** 3], w[o:o + sides[r] ** 3].astype(np.float64))
+        R.step(300)
+        assert rel_err(xs[r], R.state()[0]) <= 1e-3
+    with pytest.raises(ValueError):
+        orc.Robot(3, cls[:27], w[:27].astype(np.float64))
+    P1 = gpu_population([4], *voxel_population([4], 72))
+    P1.step(50)
+    assert np.isfinite(P1.fitness().cpu().numpy()).all()
