@@ -19,7 +19,7 @@ SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 GENOME_LEN = 8710
-NO_GRAVITY, NO_GROUND, NO_ACTUATION = 1, 2, 4
+NO_GRAVITY, NO_GROUND, NO_ACTUATION, WEIGHT_ACTUATION = 1, 2, 4, 8
 
 
 def build(force=False):
@@ -41,7 +41,8 @@ class _Params(C.Structure):
                 ("mass", C.c_double), ("voxel_len", C.c_double), ("k_ground", C.c_double),
                 ("mu", C.c_double), ("act_freq", C.c_double),
                 ("k_class", C.c_double * 5), ("a_class", C.c_double * 5),
-                ("phi_class", C.c_double * 5), ("flags", C.c_int32)]
+                ("phi_class", C.c_double * 5), ("flags", C.c_int32),
+                ("mu_static", C.c_double), ("zeta_spring", C.c_double), ("zeta_ground", C.c_double)]
 
 
 def _dp(a):
@@ -87,7 +88,9 @@ def lib():
         L.or_robot_energy.argtypes = [vp]
         L.or_robot_backward.restype = C.c_double
         L.or_robot_backward.argtypes = [vp, C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 3
-        L.or_robot_dJdw.argtypes = [vp] + [C.POINTER(C.c_double)] * 3
+        L.or_robot_backward_z.restype = C.c_double
+        L.or_robot_backward_z.argtypes = [vp, C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 3
+        L.or_robot_dJdw.argtypes = [vp] + [C.POINTER(C.c_double)] * 4
         L.or_mlp_backward.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int,
                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.or_encode.argtypes = [C.POINTER(C.c_double)] * 3
@@ -110,14 +113,26 @@ def lib():
 DEFAULTS = dict(dt=1e-4, gravity=9.81, damping=0.999, mass=0.1, voxel_len=0.1,
                 k_ground=1e5, mu=0.5, act_freq=4.0,
                 k_class=(0.0, 1e4, 1e4, 3e3, 3e4), a_class=(0.0, 0.2, -0.2, 0.0, 0.0),
-                phi_class=(0.0,) * 5, flags=0)
+                phi_class=(0.0,) * 5, flags=0, mu_static=0.0, zeta_spring=0.0, zeta_ground=0.0)
+
+# Table II as printed: stiffness 2e3 (muscle), 1e3 (soft tissue), 1e4 (bone),
+# dt 1e-5 s, muscle amplitude up to 0.25 and phase up to pi scaled by the
+# sigmoid weight, damping ratio 0.1 for the spring dashpots and the ground,
+# ground stiffness 1e5, static 0.6 / kinetic 1.0 friction.  No per-step velocity
+# damping (the dashpots dissipate); 4 Hz muscles as in the base model.
+TABLE2 = dict(dt=1e-5, gravity=9.81, damping=1.0, mass=0.1, voxel_len=0.1,
+              k_ground=1e5, mu=1.0, act_freq=4.0,
+              k_class=(0.0, 2e3, 2e3, 1e3, 1e4), a_class=(0.0, 0.25, -0.25, 0.0, 0.0),
+              phi_class=(0.0, math.pi, math.pi, 0.0, 0.0), flags=WEIGHT_ACTUATION,
+              mu_static=0.6, zeta_spring=0.1, zeta_ground=0.1)
 
 
 def make_params(**kw):
     d = dict(DEFAULTS)
     d.update(kw)
     p = _Params()
-    for k in ("dt", "gravity", "damping", "mass", "voxel_len", "k_ground", "mu", "act_freq"):
+    for k in ("dt", "gravity", "damping", "mass", "voxel_len", "k_ground", "mu", "act_freq",
+              "mu_static", "zeta_spring", "zeta_ground"):
         setattr(p, k, float(d[k]))
     p.k_class = (C.c_double * 5)(*d["k_class"])
     p.a_class = (C.c_double * 5)(*d["a_class"])
@@ -207,12 +222,19 @@ class Robot:
         J = lib().or_robot_backward(self.h, int(n_steps), float(g), _dp(gk), _dp(ga), _dp(gp))
         return J, gk, ga, gp
 
-    def dJdw(self, gk, ga):
+    def backward_z(self, n_steps, g=1.0):
+        """J and dJ/d(k, Zr, Zi) per spring, Z = k a e^{i phi} (k at fixed Z)."""
+        gk, gr, gi = (np.zeros(self.S) for _ in range(3))
+        J = lib().or_robot_backward_z(self.h, int(n_steps), float(g), _dp(gk), _dp(gr), _dp(gi))
+        return J, gk, gr, gi
+
+    def dJdw(self, gkz, gzr, gzi):
+        """dJ/dw per voxel from dJ/d(k, Zr, Zi) through the parallel-sum rule."""
         out = np.zeros(self.n ** 3)
-        rc = lib().or_robot_dJdw(self.h, _dp(np.ascontiguousarray(gk, dtype=np.float64)),
-                                 _dp(np.ascontiguousarray(ga, dtype=np.float64)), _dp(out))
+        arr = [np.ascontiguousarray(t, dtype=np.float64) for t in (gkz, gzr, gzi)]
+        rc = lib().or_robot_dJdw(self.h, *[_dp(t) for t in arr], _dp(out))
         if rc != 0:
-            raise ValueError("genome gradient needs all class phases zero")
+            raise ValueError("no genome gradient with dashpots on")
         return out
 
 
@@ -317,6 +339,6 @@ def robot_from_genome(genome, B, n, **params):
 def genome_fitness_grad(genome, B, n, n_steps, **params):
     """J = fitness after n_steps of the robot built from `genome`, and dJ/dgenome."""
     R = robot_from_genome(genome, B, n, **params)
-    J, gk, ga, gp = R.backward(n_steps)
-    dJdw = R.dJdw(gk, ga)
+    J, gk, gr, gi = R.backward_z(n_steps)
+    dJdw = R.dJdw(gk, gr, gi)
     return J, mlp_backward(genome, B, n, dJdw)

@@ -37,6 +37,9 @@
 #define OR_NO_GRAVITY 1
 #define OR_NO_GROUND 2
 #define OR_NO_ACTUATION 4
+/* Table II material model: the sigmoid weight also scales each muscle voxel's
+ * actuation amplitude and phase (Sec. II-C; Table II maximum amplitude and phase) */
+#define OR_WEIGHT_ACTUATION 8
 
 /* genome layout: W1[64][64] b1[64] W2[64][64] b2[64] W3[6][64] b3[6] */
 #define OR_PE_M 32
@@ -63,6 +66,10 @@ typedef struct {
     double a_class[5];  /* actuation amplitude per class (relative to L0) */
     double phi_class[5];/* actuation phase per class [rad] */
     int32_t flags;
+    /* Table II extensions; zero gives the base model */
+    double mu_static;   /* static friction coefficient (acts only above mu) */
+    double zeta_spring; /* damping ratio of the dashpot beside every spring */
+    double zeta_ground; /* damping ratio of the ground contact */
 } or_params;
 
 int or_genome_len(void) { return OR_GENOME_LEN; }
@@ -202,6 +209,7 @@ typedef struct {
     int32_t *lat_node; /* [N^3] node id or -1 */
     int32_t *ij;       /* [S][2] node ids, ij[2s] < ij[2s+1] */
     double *L0, *k, *a, *phi; /* [S] rest length, stiffness, amplitude, phase */
+    double *cd;        /* [S] dashpot coefficient [N s/m] */
     int32_t *sv_ptr;   /* [S+1] range of voxels holding each spring */
     int32_t *sv;       /* voxel ids */
     double *x, *v, *x0;/* [M][3] */
@@ -219,22 +227,42 @@ static int cmp_pair(const void *A, const void *B)
     return (a->vox > b->vox) - (a->vox < b->vox);
 }
 
+/* Actuation amplitude and phase of one voxel of class c and weight w.  Base
+ * model: the class values.  Table II model: the weight scales both, up to the
+ * class maxima. */
+static void voxel_actuation(const or_params *p, int c, double w, double *amp, double *ph)
+{
+    if (p->flags & OR_WEIGHT_ACTUATION) {
+        *amp = w * p->a_class[c];
+        *ph = w * p->phi_class[c];
+    } else {
+        *amp = p->a_class[c];
+        *ph = p->phi_class[c];
+    }
+}
+
 /* Spring parameters by the parallel-sum rule: a spring shared by several
  * kept voxels is the parallel combination of their springs, so
- *   k_s = sum_v k_c(v) w(v),   k_s a_s e^{i phi_s} = sum_v k_c(v) w(v) a_c(v) e^{i phi_c(v)}.
+ *   k_s = sum_v k_c(v) w(v),   k_s a_s e^{i phi_s} = sum_v k_c(v) w(v) a_v e^{i phi_v},
+ * and the dashpots beside them add too: c_s = sum_v zeta sqrt(2 m k_c(v) w(v))
+ * (damping ratio zeta of each voxel spring between two nodes of mass m).
  * When every term is in phase the amplitude is kept signed with phi = 0. */
 static void spring_params_from_voxels(or_robot *R, int s)
 {
-    double ks = 0.0, zr = 0.0, zi = 0.0;
+    double ks = 0.0, zr = 0.0, zi = 0.0, cs = 0.0;
     for (int q = R->sv_ptr[s]; q < R->sv_ptr[s + 1]; ++q) {
         int v = R->sv[q];
         int c = R->kept[v];
         double kw = R->p.k_class[c] * R->w[v];
+        double amp, ph;
+        voxel_actuation(&R->p, c, R->w[v], &amp, &ph);
         ks += kw;
-        zr += kw * R->p.a_class[c] * cos(R->p.phi_class[c]);
-        zi += kw * R->p.a_class[c] * sin(R->p.phi_class[c]);
+        zr += kw * amp * cos(ph);
+        zi += kw * amp * sin(ph);
+        cs += R->p.zeta_spring * sqrt(2.0 * R->p.mass * kw);
     }
     R->k[s] = ks;
+    R->cd[s] = cs;
     if (ks == 0.0) { R->a[s] = 0.0; R->phi[s] = 0.0; }
     else if (zi == 0.0) { R->a[s] = zr / ks; R->phi[s] = 0.0; }
     else { R->a[s] = sqrt(zr * zr + zi * zi) / ks; R->phi[s] = atan2(zi, zr); }
@@ -265,7 +293,7 @@ void or_robot_destroy(or_robot *R)
 {
     if (!R) return;
     free(R->kept); free(R->w); free(R->node_lat); free(R->lat_node); free(R->ij);
-    free(R->L0); free(R->k); free(R->a); free(R->phi); free(R->sv_ptr); free(R->sv);
+    free(R->L0); free(R->k); free(R->a); free(R->phi); free(R->cd); free(R->sv_ptr); free(R->sv);
     free(R->x); free(R->v); free(R->x0);
     free(R);
 }
@@ -336,6 +364,7 @@ or_robot *or_robot_create(const or_params *p, int n, const uint8_t *cls, const d
     R->k = (double *)malloc(sizeof(double) * S);
     R->a = (double *)malloc(sizeof(double) * S);
     R->phi = (double *)malloc(sizeof(double) * S);
+    R->cd = (double *)malloc(sizeof(double) * S);
     R->sv_ptr = (int32_t *)malloc(sizeof(int32_t) * (S + 1));
     R->sv = (int32_t *)malloc(sizeof(int32_t) * np);
     int s = -1;
@@ -422,10 +451,26 @@ static double rest_length(const or_robot *R, int s, int64_t step)
     return R->L0[s] * (1.0 + R->a[s] * sin(2.0 * OR_PI * R->p.act_freq * t + R->phi[s]));
 }
 
-/* Total force on every node at positions x, time step `step`:
- * Hooke springs f_s = k_s (r - L_s) along the spring, gravity -m g e_z, and a
- * penalty ground normal k_ground * max(0, -z). */
-static void forces(const or_robot *R, const double *x, int64_t step, double *F)
+/* Ground normal force on a node at height z with vertical velocity vz:
+ * zero above the plane; below it the penalty k_ground (-z) plus, in the
+ * Table II model, a contact damper -c_g vz with c_g = 2 zeta_g sqrt(k_ground m),
+ * never pulling the node down (the total is clamped at zero). */
+static double ground_normal(const or_robot *R, double z, double vz)
+{
+    if ((R->p.flags & OR_NO_GROUND) || !(z < 0.0)) return 0.0;
+    double N = R->p.k_ground * (-z);
+    if (R->p.zeta_ground != 0.0) {
+        N -= 2.0 * R->p.zeta_ground * sqrt(R->p.k_ground * R->p.mass) * vz;
+        if (N < 0.0) N = 0.0;
+    }
+    return N;
+}
+
+/* Total force on every node at state (x, v), time step `step`:
+ * Hooke springs f_s = k_s (r - L_s) along the spring, a dashpot
+ * c_s (v_j - v_i).d^ beside each spring, gravity -m g e_z, and the ground
+ * normal. */
+static void forces(const or_robot *R, const double *x, const double *v, int64_t step, double *F)
 {
     memset(F, 0, sizeof(double) * 3 * R->M);
     for (int s = 0; s < R->S; ++s) {
@@ -434,6 +479,11 @@ static void forces(const or_robot *R, const double *x, int64_t step, double *F)
         double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         if (r < 1e-9) continue; /* a collapsed spring has no direction */
         double f = R->k[s] * (r - rest_length(R, s, step));
+        if (R->cd[s] != 0.0) {
+            double rate = 0.0; /* (v_j - v_i) . d / r */
+            for (int q = 0; q < 3; ++q) rate += (v[3 * j + q] - v[3 * i + q]) * d[q] / r;
+            f += R->cd[s] * rate;
+        }
         for (int q = 0; q < 3; ++q) {
             F[3 * i + q] += f * d[q] / r;
             F[3 * j + q] -= f * d[q] / r;
@@ -441,20 +491,22 @@ static void forces(const or_robot *R, const double *x, int64_t step, double *F)
     }
     for (int i = 0; i < R->M; ++i) {
         if (!(R->p.flags & OR_NO_GRAVITY)) F[3 * i + 2] -= R->p.mass * R->p.gravity;
-        if (!(R->p.flags & OR_NO_GROUND) && x[3 * i + 2] < 0.0) F[3 * i + 2] += R->p.k_ground * (-x[3 * i + 2]);
+        F[3 * i + 2] += ground_normal(R, x[3 * i + 2], v[3 * i + 2]);
     }
 }
 
-/* Velocity-level Coulomb friction for a node below the ground plane: the
- * tangential velocity loses at most dv = mu * N * dt / m, N = k_ground*(-z),
- * and is never reversed. */
-static void friction(const or_robot *R, double z, double *vp)
+/* Velocity-level Coulomb friction for a node pressed on the ground with
+ * normal force N: the tangential velocity u sticks (becomes zero) when
+ * |u| <= max(mu_s, mu_k) N dt / m, and otherwise loses mu_k N dt / m of its
+ * length without reversing.  mu_s only matters when it exceeds mu_k. */
+static void friction(const or_robot *R, double N, double *vp)
 {
-    if ((R->p.flags & OR_NO_GROUND) || !(z < 0.0)) return;
-    double dv = R->p.mu * R->p.k_ground * (-z) * R->p.dt / R->p.mass;
+    if (!(N > 0.0)) return;
+    double dvk = R->p.mu * N * R->p.dt / R->p.mass;
+    double dvs = R->p.mu_static * N * R->p.dt / R->p.mass;
     double u = sqrt(vp[0] * vp[0] + vp[1] * vp[1]);
-    if (u <= dv) { vp[0] = 0.0; vp[1] = 0.0; }
-    else { vp[0] *= (1.0 - dv / u); vp[1] *= (1.0 - dv / u); }
+    if (u <= dvk || u <= dvs) { vp[0] = 0.0; vp[1] = 0.0; }
+    else { vp[0] *= (1.0 - dvk / u); vp[1] *= (1.0 - dvk / u); }
 }
 
 static int robot_state_bad(const or_robot *R)
@@ -470,11 +522,12 @@ static int robot_state_bad(const or_robot *R)
  *   v_{n+1} = damping * v';  x_{n+1} = x_n + dt v_{n+1}. */
 static void step_once(or_robot *R, double *F)
 {
-    forces(R, R->x, R->step, F);
+    forces(R, R->x, R->v, R->step, F);
     for (int i = 0; i < R->M; ++i) {
         double vp[3];
+        double N = ground_normal(R, R->x[3 * i + 2], R->v[3 * i + 2]);
         for (int q = 0; q < 3; ++q) vp[q] = R->v[3 * i + q] + R->p.dt * F[3 * i + q] / R->p.mass;
-        friction(R, R->x[3 * i + 2], vp);
+        friction(R, N, vp);
         for (int q = 0; q < 3; ++q) {
             R->v[3 * i + q] = R->p.damping * vp[q];
             R->x[3 * i + q] += R->p.dt * R->v[3 * i + q];
@@ -561,13 +614,19 @@ double or_robot_energy(const or_robot *R)
 /* ------------------------------------------------------------------------ */
 
 /* Gradient of J = g * fitness after n_steps from the robot's current state
- * with respect to every spring's (k, a, phi), by reverse accumulation through
+ * with respect to every spring's parameters, by reverse accumulation through
  * each forward operation (every state stored).  Contact and friction branches
  * are the ones the forward run took.  The robot itself is not modified.
- * Returns J, or NaN when the run diverges. */
-double or_robot_backward(const or_robot *R, int n_steps, double g, double *gk, double *ga, double *gphi)
+ * Two parametrisations of the actuated rest length
+ *   L = L0 (1 + a sin(w t + phi)) = L0 + L0 (Zr sin wt + Zi cos wt) / k,
+ * Z = k a e^{i phi}, are reported: (gk, ga, gphi) = dJ/d(k, a, phi) and
+ * (gkz, gzr, gzi) = dJ/d(k, Zr, Zi) (k at fixed Z); any output may be NULL.
+ * Returns J; NaN when a spring or ground dashpot is on (no adjoint for them). */
+static double backward_impl(const or_robot *R, int n_steps, double g, double *gk, double *ga, double *gphi,
+                            double *gkz, double *gzr, double *gzi)
 {
     int M = R->M, S = R->S;
+    if (R->p.zeta_spring != 0.0 || R->p.zeta_ground != 0.0) return NAN;
     const or_params *p = &R->p;
     double m = p->mass, dt = p->dt;
     int ground = !(p->flags & OR_NO_GROUND);
@@ -594,14 +653,14 @@ double or_robot_backward(const or_robot *R, int n_steps, double g, double *gk, d
     double *lx = (double *)calloc(3 * M, sizeof(double));
     double *lv = (double *)calloc(3 * M, sizeof(double));
     double *lF = (double *)malloc(sizeof(double) * 3 * M);
-    for (int s = 0; s < S; ++s) { gk[s] = 0.0; ga[s] = 0.0; gphi[s] = 0.0; }
+    double *acc = (double *)calloc(6 * (size_t)S, sizeof(double)); /* gk ga gphi gkz gzr gzi */
     /* terminal condition: dJ/dx_N = g/M e_x, dJ/dv_N = 0 */
     for (int i = 0; i < M; ++i) lx[3 * i] = g / M;
 
     for (int t = n_steps - 1; t >= 0; --t) {
         const double *x = xs + (size_t)3 * M * t, *v = vs + (size_t)3 * M * t;
         int64_t step = R->step + t;
-        forces(R, x, step, F);
+        forces(R, x, v, step, F);
         for (int i = 0; i < M; ++i) {
             double lvt[3], vp[3];
             /* x_{n+1} = x_n + dt v_{n+1}: v_{n+1} collects dt * lambda_x */
@@ -613,8 +672,9 @@ double or_robot_backward(const or_robot *R, int n_steps, double g, double *gk, d
             double z = x[3 * i + 2];
             if (ground && z < 0.0) {
                 double dv = p->mu * p->k_ground * (-z) * dt / m;
+                double dvs = p->mu_static * p->k_ground * (-z) * dt / m;
                 double u = sqrt(vp[0] * vp[0] + vp[1] * vp[1]);
-                if (u <= dv) {
+                if (u <= dv || u <= dvs) {
                     lvt[0] = 0.0;
                     lvt[1] = 0.0;
                 } else {
@@ -639,6 +699,7 @@ double or_robot_backward(const or_robot *R, int n_steps, double g, double *gk, d
         }
         /* springs */
         double wt = 2.0 * OR_PI * p->act_freq * (double)step * dt;
+        double Sw = act ? sin(wt) : 0.0, Cw = act ? cos(wt) : 0.0;
         for (int s = 0; s < S; ++s) {
             int i = R->ij[2 * s], j = R->ij[2 * s + 1];
             double d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1], x[3 * j + 2] - x[3 * i + 2]};
@@ -656,34 +717,65 @@ double or_robot_backward(const or_robot *R, int n_steps, double g, double *gk, d
                 lx[3 * i + q] += Ku;
                 lx[3 * j + q] -= Ku;
             }
-            gk[s] += -(r - L) * du;
+            double *A = acc + 6 * (size_t)s;
+            A[0] += -(r - L) * du;
+            A[3] += -(r - R->L0[s]) * du;
             if (act) {
                 double gL = R->k[s] * du;
-                ga[s] += gL * R->L0[s] * sn;
-                gphi[s] += gL * R->L0[s] * R->a[s] * cs;
+                A[1] += gL * R->L0[s] * sn;
+                A[2] += gL * R->L0[s] * R->a[s] * cs;
+                A[4] += R->L0[s] * Sw * du;
+                A[5] += R->L0[s] * Cw * du;
             }
         }
     }
+    double *out[6] = {gk, ga, gphi, gkz, gzr, gzi};
+    for (int q = 0; q < 6; ++q)
+        if (out[q])
+            for (int s = 0; s < S; ++s) out[q][s] = acc[6 * (size_t)s + q];
+    free(acc);
     free(xs); free(vs); free(F); free(tmp.x); free(tmp.v); free(lx); free(lv); free(lF);
     return J;
 }
 
-/* dJ/dw for every voxel, from per-spring gradients through the sum rule
- * (all class phases zero):  dk_s/dw_v = k_c(v),  da_s/dw_v = k_c(v) (a_c(v) - a_s) / k_s. */
-int or_robot_dJdw(const or_robot *R, const double *gk, const double *ga, double *dJdw)
+double or_robot_backward(const or_robot *R, int n_steps, double g, double *gk, double *ga, double *gphi)
 {
-    for (int c = 0; c < 5; ++c)
-        if (R->p.phi_class[c] != 0.0) return -1;
+    return backward_impl(R, n_steps, g, gk, ga, gphi, NULL, NULL, NULL);
+}
+
+double or_robot_backward_z(const or_robot *R, int n_steps, double g, double *gkz, double *gzr, double *gzi)
+{
+    return backward_impl(R, n_steps, g, NULL, NULL, NULL, gkz, gzr, gzi);
+}
+
+/* dJ/dw for every voxel from the per-spring gradients dJ/d(k, Zr, Zi) through
+ * the sum rule: voxel v adds k_c w to k_s and k_c w amp_v e^{i ph_v} to Z_s of
+ * each of its springs, so
+ *   dJ/dw_v = sum_{s of v} k_c dJ/dk_s + dRe(.)/dw dJ/dZr_s + dIm(.)/dw dJ/dZi_s
+ * with, for the base model (amp, ph fixed per class),
+ *   d(k_c w a_c e^{i phi_c})/dw = k_c a_c e^{i phi_c},
+ * and for the Table II model (amp = w a_c, ph = w phi_c),
+ *   d(k_c a_c w^2 e^{i w phi_c})/dw = k_c a_c (2 w + i w^2 phi_c) e^{i w phi_c}.
+ * Returns -1 when a dashpot is on (its coefficient also depends on w). */
+int or_robot_dJdw(const or_robot *R, const double *gkz, const double *gzr, const double *gzi, double *dJdw)
+{
+    if (R->p.zeta_spring != 0.0 || R->p.zeta_ground != 0.0) return -1;
     int nv = R->n * R->n * R->n;
     for (int v = 0; v < nv; ++v) dJdw[v] = 0.0;
     for (int s = 0; s < R->S; ++s) {
         for (int q = R->sv_ptr[s]; q < R->sv_ptr[s + 1]; ++q) {
             int v = R->sv[q];
             int c = R->kept[v];
-            double kc = R->p.k_class[c];
-            double t = gk[s];
-            if (R->k[s] != 0.0) t += (R->p.a_class[c] - R->a[s]) / R->k[s] * ga[s];
-            dJdw[v] += kc * t;
+            double kc = R->p.k_class[c], ac = R->p.a_class[c], pc = R->p.phi_class[c], w = R->w[v];
+            double dzr, dzi;
+            if (R->p.flags & OR_WEIGHT_ACTUATION) {
+                dzr = kc * ac * (2.0 * w * cos(w * pc) - w * w * pc * sin(w * pc));
+                dzi = kc * ac * (2.0 * w * sin(w * pc) + w * w * pc * cos(w * pc));
+            } else {
+                dzr = kc * ac * cos(pc);
+                dzi = kc * ac * sin(pc);
+            }
+            dJdw[v] += kc * gkz[s] + dzr * gzr[s] + dzi * gzi[s];
         }
     }
     return 0;

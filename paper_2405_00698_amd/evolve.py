@@ -100,6 +100,16 @@ def evolve(sides, generations=100, sim_steps=10000, seed_genome=1, seed_ga=3, si
     return history
 
 
+def sigma_sweep(sigmas, sides, repeats=1, **kw):
+    """Sweep the standard deviation of the encoding matrix B (Sec. II-B states
+    that it was chosen by a sweep but gives no values): runs `evolve` once per
+    (sigma, repeat), the repeat changing the genome seed, and returns
+    {sigma: [history, ...]}."""
+    seed0 = kw.pop("seed_genome", 1)
+    return {float(s): [evolve(sides, sigma_B=float(s), seed_genome=seed0 + r, **kw) for r in range(repeats)]
+            for s in sigmas}
+
+
 if __name__ == "__main__":
     import argparse
     import sys
@@ -111,6 +121,13 @@ if __name__ == "__main__":
     ap.add_argument("--sigma-B", type=float, default=1.0, help="standard deviation of the encoding matrix B")
     ap.add_argument("--supervisor", action="store_true", help="use the rule-based stand-in for the LLM supervisor")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--repeats", type=int, default=1, help="independent runs (genome seeds seed, seed+1, ...)")
+    ap.add_argument("--sigma-sweep", default=None, help="comma-separated values of sigma_B to sweep")
     a = ap.parse_args()
-    evolve([a.side] * a.robots, a.generations, a.sim_steps, seed_genome=a.seed, sigma_B=a.sigma_B,
-           supervisor=rule_supervisor if a.supervisor else None, log=sys.stdout)
+    sup = rule_supervisor if a.supervisor else None
+    sigmas = [float(q) for q in a.sigma_sweep.split(",")] if a.sigma_sweep else [a.sigma_B]
+    for s in sigmas:
+        for r in range(a.repeats):
+            sys.stdout.write(json.dumps({"sigma_B": s, "repeat": r}) + "\n")
+            evolve([a.side] * a.robots, a.generations, a.sim_steps, seed_genome=a.seed + r, sigma_B=s,
+                   supervisor=sup, log=sys.stdout)
