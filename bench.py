@@ -93,7 +93,7 @@ def plain_baseline(api, inputs, torch, R, n, steps, prec):
     """The same workload stepped by the per-step-launch kernel (state in HBM)."""
     from paper_2405_00698_amd import SR_STEP_PLAIN
     dev = torch.device("cuda:0")
-    P = api.Population(sides)
+    P = api.Population([n] * R)
     P.set_step_config(SR_STEP_PLAIN)
     P.build_from_genomes(torch.from_numpy(inputs.random_genomes(R)).to(dev),
                          torch.from_numpy(inputs.gaussian_B()).to(dev), prec)
@@ -106,6 +106,32 @@ def plain_baseline(api, inputs, torch, R, n, steps, prec):
     dt = time.perf_counter() - t
     P.close()
     return S * steps / dt
+
+
+def model_rates(api, inputs, torch, R, n, steps, prec):
+    """Step-kernel throughput of the base model and of the Table II model
+    (weight-scaled muscles, spring and ground dashpots, static/kinetic
+    friction) on the same genomes, each with its tuned kernel."""
+    from paper_2405_00698_amd import tune, _lib
+    dev = torch.device("cuda:0")
+    G = torch.from_numpy(inputs.random_genomes(R)).to(dev)
+    B = torch.from_numpy(inputs.gaussian_B()).to(dev)
+    out = {"workload": "%d robots on %d^3 grids, %d steps" % (R, n, steps)}
+    for name, params in (("base", _lib.default_params()), ("table2", _lib.table2_params())):
+        P = api.Population([n] * R, params=params)
+        P.build_from_genomes(G, B, prec)
+        cfg = tune.tune(P, steps=200, cache_path="/tmp/softrobot_tune.json")
+        S = sum(P.counts()[1])
+        P.step(20)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        P.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out[name] = {"spring_updates_per_s": S * steps / dt, "kernel": P.kernel_config(n),
+                     "tuned_s": cfg[n][2]}
+        P.close()
+    return out
 
 
 def adjoint_ratio(api, inputs, torch):
@@ -265,6 +291,8 @@ def main():
         out["per_step_launch_spring_updates_per_s"] = pl
         out["persistent_over_per_step_launch"] = (su_per_launch / kern_s) / pl
         out["adjoint_forward_ratio"] = adjoint_ratio(api, inputs, torch)
+        out["material_models"] = [model_rates(api, inputs, torch, 4096, 5, 10000, prec),
+                                  model_rates(api, inputs, torch, 1024, 8, 5000, prec)]
     if not args.no_cpu_baseline and args.workload == "uniform":
         out["cpu_baseline"] = cpu_baseline(args, G, B)
     print(json.dumps(out), flush=True)

@@ -47,6 +47,9 @@ extern "C" {
 #define SR_NO_GRAVITY 1u
 #define SR_NO_GROUND 2u
 #define SR_NO_ACTUATION 4u
+/* Table II material model: a muscle voxel's actuation amplitude and phase are
+ * its class values (the maxima) times its sigmoid weight (Sec. II-C). */
+#define SR_WEIGHT_ACTUATION 8u
 
 #define SR_GENOME_LEN 8710 /* W1[64][64] b1[64] W2[64][64] b2[64] W3[6][64] b3[6] */
 #define SR_PE_M 32         /* rows of the encoding matrix B (Eq. (1)), d = 3 */
@@ -79,7 +82,19 @@ typedef struct {
     float k_class[5];   /* stiffness per material class [N/m] */
     float a_class[5];   /* actuation amplitude per class, relative to L0 */
     float phi_class[5]; /* actuation phase per class [rad] */
-    uint32_t flags;     /* SR_NO_* test modes */
+    uint32_t flags;     /* SR_NO_* test modes, SR_WEIGHT_ACTUATION */
+    /* Table II contact and damping terms; zero leaves them out.
+     * mu_static: a node pressed on the ground sticks when its tangential speed
+     *   is within max(mu_static, mu) N dt / m (N the normal force); otherwise
+     *   kinetic friction mu acts.  Only matters when above mu.
+     * zeta_spring: damping ratio of a dashpot beside each voxel spring,
+     *   c = zeta sqrt(2 m k_c w); a shared spring sums its voxels' dashpots.
+     * zeta_ground: damping ratio of the ground contact, c_g = 2 zeta sqrt(k_ground m);
+     *   the normal force k_ground (-z) - c_g v_z is clamped at zero. */
+    float mu_static;
+    float zeta_spring;
+    float zeta_ground;
+    float reserved;
 } sr_sim_params;
 
 /* GA rates (Table I: mutation rate 0.1, crossover rate 0.4, elite 0.3;
@@ -103,6 +118,13 @@ int sr_version(void);
 
 /* Fills *out with the defaults above. */
 int sr_default_params(sr_sim_params *out);
+
+/* Fills *out with Table II as printed: class stiffness {0, 2e3, 2e3, 1e3, 1e4} N/m,
+ * dt = 1e-5 s, muscle amplitude up to 0.25 and phase up to pi scaled by the
+ * voxel weight (SR_WEIGHT_ACTUATION; expanding +0.25, contracting -0.25),
+ * spring and ground damping ratio 0.1, static friction 0.6 and kinetic 1.0,
+ * no per-step velocity damping; 4 Hz muscles as in the defaults. */
+int sr_table2_params(sr_sim_params *out);
 
 /* Creates a population of n_robots robots; grid_side (host [n_robots]) gives
  * each robot's side n, 1..SR_MAX_SIDE.  stream: hipStream_t for every call on
@@ -155,19 +177,24 @@ int pop_set_graphs(sr_pop *pop, int32_t enable);
  * workgroup and variant (0 recompute every spring force at both ends,
  * 1 exchange spring coefficients through LDS, 2 exchange in two direction
  * chunks; +4 bounds the LDS loads in flight to save registers; +8 reads
- * positions with 12-byte instead of 16-byte LDS loads).  All variants
- * give bit-identical results.  SR_EUNSUPPORTED for a combination the library
- * lacks. */
+ * positions with 12-byte instead of 16-byte LDS loads; +16 marks the kernels
+ * with spring dashpots, which also share velocities through LDS: a population
+ * with zeta_spring != 0 accepts only those, any other population only the
+ * rest).  All variants of one kind give bit-identical results.
+ * SR_EUNSUPPORTED for a combination the library lacks or that does not match
+ * the population's physics. */
 int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t variant);
 /* The persistent kernel configuration in use for side n (host outputs). */
 int pop_get_persist_variant(sr_pop *pop, int32_t n, int32_t *block, int32_t *variant);
 
 /* Advances every robot n_steps >= 0 steps.  Step n -> n+1 (t_n = n dt):
  * spring forces k (r - L(t_n)) along each spring with L = L0 (1 + a sin(2 pi f
- * t_n + phi)), gravity -m g e_z, ground normal k_ground max(0, -z); v' = v +
- * dt F / m; where z < 0 the horizontal part of v' loses at most mu k_ground
- * (-z) dt / m and never reverses; v <- damping v'; x <- x + dt v.  All forces
- * use the positions of step n.  A robot whose state is non-finite or beyond
+ * t_n + phi)) plus, with zeta_spring, the dashpot c (v_j - v_i).d^; gravity
+ * -m g e_z; ground normal N = k_ground max(0, -z) (minus the contact damper
+ * c_g v_z with zeta_ground, clamped at zero); v' = v + dt F / m; where N > 0
+ * the horizontal part of v' sticks at zero within max(mu_static, mu) N dt / m
+ * and otherwise loses mu N dt / m without reversing; v <- damping v';
+ * x <- x + dt v.  All forces use the state of step n.  A robot whose state is non-finite or beyond
  * 1e3 n voxel lengths at the end of a launch is flagged diverged and frozen. */
 int pop_step(sr_pop *pop, int32_t n_steps);
 
@@ -190,8 +217,10 @@ int pop_record(sr_pop *pop, int32_t checkpoint_every, int32_t max_steps);
  * canonical spring order, NULL to skip): dJ/dk, dJ/da, dJ/dphi per spring.
  * g_genome (dev [n_robots][SR_GENOME_LEN] or NULL): dJ/dgenome through the
  * sigmoid weight head, the parallel-sum rule and the MLP in FP32 (the class
- * head, the component step and the topology carry no gradient); needs the
- * genomes and B (dev) of the build and every class phase zero, else
+ * head, the component step and the topology carry no gradient; with
+ * SR_WEIGHT_ACTUATION also through the weight-scaled amplitude and phase);
+ * needs the genomes and B (dev) of the build.  Populations with spring or
+ * ground dashpots (zeta_spring or zeta_ground != 0) have no adjoint:
  * SR_EUNSUPPORTED.  SR_ESTATE without a recorded run.  Gradients of a
  * diverged robot are undefined. */
 int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, float *g_phi,

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsoftrobot.so")
 
 SR_OK, SR_EINVAL, SR_ENOMEM, SR_EHIP, SR_ESTATE, SR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-SR_NO_GRAVITY, SR_NO_GROUND, SR_NO_ACTUATION = 1, 2, 4
+SR_NO_GRAVITY, SR_NO_GROUND, SR_NO_ACTUATION, SR_WEIGHT_ACTUATION = 1, 2, 4, 8
 SR_QUERY_FP32, SR_QUERY_BF16 = 0, 1
 SR_STEP_AUTO, SR_STEP_PERSISTENT, SR_STEP_PLAIN = 0, 1, 2
 GENOME_LEN = 8710
@@ -17,7 +17,8 @@ class SimParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("gravity", C.c_float), ("damping", C.c_float), ("mass", C.c_float),
                 ("voxel_len", C.c_float), ("k_ground", C.c_float), ("mu", C.c_float), ("act_freq", C.c_float),
                 ("k_class", C.c_float * 5), ("a_class", C.c_float * 5), ("phi_class", C.c_float * 5),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("mu_static", C.c_float), ("zeta_spring", C.c_float),
+                ("zeta_ground", C.c_float), ("reserved", C.c_float)]
 
 
 class GAParams(C.Structure):
@@ -40,6 +41,7 @@ _SIGS = {
     "sr_last_error": ([], C.c_char_p),
     "sr_version": ([], C.c_int),
     "sr_default_params": ([C.POINTER(SimParams)], C.c_int),
+    "sr_table2_params": ([C.POINTER(SimParams)], C.c_int),
     "pop_create": ([C.POINTER(SimParams), C.c_int32, C.POINTER(C.c_int32), P, C.POINTER(P)], C.c_int),
     "pop_destroy": ([P], C.c_int),
     "pop_build_from_voxels": ([P, P, P], C.c_int),
@@ -95,6 +97,17 @@ def check(rc):
 def default_params(**overrides):
     p = SimParams()
     check(load().sr_default_params(C.byref(p)))
+    return _override(p, overrides)
+
+
+def table2_params(**overrides):
+    """Table II material and contact model (sr_table2_params), with overrides."""
+    p = SimParams()
+    check(load().sr_table2_params(C.byref(p)))
+    return _override(p, overrides)
+
+
+def _override(p, overrides):
     for k, v in overrides.items():
         if k in ("k_class", "a_class", "phi_class"):
             setattr(p, k, (C.c_float * 5)(*v))

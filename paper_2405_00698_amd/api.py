@@ -45,6 +45,8 @@ class Population:
         self.h = h
         self.n_vox = sum(n ** 3 for n in self.sides)
         self._counts = None
+        # spring dashpots select the +16 persistent kernels
+        self.dashpots = self.params.zeta_spring != 0.0
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     if (below) {
                         const float dv = c.mu_kc_dt_m * (-X.z);
                         const float u = sqrtf(fmaf(VP.y, VP.y, VP.x * VP.x));
-                        if (u <= dv) {
+                        if (u <= fmaxf(dv, c.mus_kc_dt_m * (-X.z))) {
                             ux = 0.f;
                             uy = 0.f;
                         } else {
@@ -320,17 +320,23 @@ __global__ void k_adj_springs(const RobotInfo *robots, int total_slots, const in
     }
 }
 
-// dJ/dw per voxel through the parallel-sum rule (all class phases zero):
-// dk_s/dw_v = k_c(v), da_s/dw_v = k_c(v) (a_c(v) - a_s) / k_s, summed over the
-// 28 springs of the kept voxel.
+// dJ/dw per voxel through the parallel-sum rule.  Write Z = k a e^{i phi} for a
+// spring, so k L(t) = k L0 + L0 (Re Z sin wt + Im Z cos wt): then dJ/dRe Z =
+// L0 gs / k, dJ/dIm Z = L0 gc / k and, at fixed Z, dJ/dk = gk - (kal gs + kbe gc) / k^2
+// (gk is dJ/dk at fixed a, phi; gs, gc the sums of dJ/dL k sin wt, k cos wt).
+// Voxel v adds k_c w to k and k_c w amp e^{i ph} to Z of each of its 28 springs,
+// with (amp, ph) = (a_c, phi_c), or (w a_c, w phi_c) under weight-scaled
+// actuation, whose w-derivative is k_c a_c (2 w + i w^2 phi_c) e^{i w phi_c}.
 struct DwArgs {
     const RobotInfo *robots;
     int total_vox;
     const int32_t *vox_robot;
     const uint8_t *kept;
+    const float *w;
     Planes pl;
-    const float *gk, *gs;
-    float k_class[5], a_class[5];
+    const float *gk, *gs, *gc;
+    float k_class[5], a_class[5], phi_class[5];
+    int weight_act;
     float voxel_len;
     float *dJdw;
 };
@@ -348,7 +354,16 @@ __global__ void k_adj_dw(DwArgs A) {
     }
     const int n = ri.n, N = ri.N;
     const int i = v % n, j = (v / n) % n, kk = v / (n * n);
-    const float kc = A.k_class[c], ac = A.a_class[c];
+    const float kc = A.k_class[c], ac = A.a_class[c], pc = A.phi_class[c], wv = A.w[gv];
+    float dzr, dzi;  // d(k_c w amp e^{i ph})/dw
+    if (A.weight_act) {
+        const float cs = cosf(wv * pc), sn = sinf(wv * pc);
+        dzr = kc * ac * (2.f * wv * cs - wv * wv * pc * sn);
+        dzi = kc * ac * (2.f * wv * sn + wv * wv * pc * cs);
+    } else {
+        dzr = kc * ac * cosf(pc);
+        dzi = kc * ac * sinf(pc);
+    }
     float sum = 0.f;
     for (int c1 = 0; c1 < 8; ++c1) {
         const int a1 = i + (c1 & 1), b1 = j + ((c1 >> 1) & 1), z1 = kk + (c1 >> 2);
@@ -365,11 +380,14 @@ __global__ void k_adj_dw(DwArgs A) {
             const int pi = NDIR * ri.slot_base + d * ri.slots + l1;
             const float ks = A.pl.k[pi];
             const float L0 = A.voxel_len * sqrtf((float)dir_len2(d));
-            const float as = A.pl.kL0[pi] != 0.f ? A.pl.kal[pi] / A.pl.kL0[pi] : 0.f;
-            const float ga = L0 * A.gs[pi];
-            float t = A.gk[pi];
-            if (ks != 0.f) t += (ac - as) / ks * ga;
-            sum += kc * t;
+            const float gs = A.gs[pi], gc = A.gc[pi];
+            float t = kc * A.gk[pi];
+            if (ks != 0.f) {
+                const float ik = 1.f / ks;
+                t -= kc * (A.pl.kal[pi] * gs + A.pl.kbe[pi] * gc) * ik * ik;
+                t += L0 * ik * (dzr * gs + dzi * gc);
+            }
+            sum += t;
         }
     }
     A.dJdw[gv] = sum;
@@ -575,21 +593,25 @@ hipError_t launch_adj_springs(const RobotInfo *robots, int total_slots, const in
 }
 
 hipError_t launch_adj_genome(const RobotInfo *robots, int R, int total_vox, const int32_t *vox_robot,
-                             const uint8_t *kept, Planes pl, const float *gk, const float *gs,
-                             const sr_sim_params &p, const float *genomes, const float *B, float *dJdw, float *g_gen,
-                             hipStream_t st) {
+                             const uint8_t *kept, const float *w, Planes pl, const float *gk, const float *gs,
+                             const float *gc, const sr_sim_params &p, const float *genomes, const float *B, float *dJdw,
+                             float *g_gen, hipStream_t st) {
     DwArgs A;
     A.robots = robots;
     A.total_vox = total_vox;
     A.vox_robot = vox_robot;
     A.kept = kept;
+    A.w = w;
     A.pl = pl;
     A.gk = gk;
     A.gs = gs;
+    A.gc = gc;
     for (int c = 0; c < 5; ++c) {
         A.k_class[c] = p.k_class[c];
         A.a_class[c] = p.a_class[c];
+        A.phi_class[c] = p.phi_class[c];
     }
+    A.weight_act = (p.flags & SR_WEIGHT_ACTUATION) != 0;
     A.voxel_len = p.voxel_len;
     A.dJdw = dJdw;
     hipLaunchKernelGGL(k_adj_dw, dim3((total_vox + 255) / 256), dim3(256), 0, st, A);

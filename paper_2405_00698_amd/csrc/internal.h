@@ -47,9 +47,10 @@ struct RobotInfo {
 //   kL0   k * L0
 //   kal   k * L0 * a cos(phi)   (coefficient of sin(w t) in k L(t))
 //   kbe   k * L0 * a sin(phi)   (coefficient of cos(w t))
-// so that k L(t) = kL0 + kal sin(w t) + kbe cos(w t).
+// so that k L(t) = kL0 + kal sin(w t) + kbe cos(w t); and
+//   kd    dashpot coefficient c beside the spring (Table II model; 0 otherwise).
 struct Planes {
-    float *k, *kL0, *kal, *kbe;
+    float *k, *kL0, *kal, *kbe, *kd;
 };
 
 // Node incidence for the per-step kernel: for node i of a robot (slot-space
@@ -66,7 +67,11 @@ struct Entry {
 struct SimConst {
     float dt, dt_m, damping, mg, kc, mu_kc_dt_m, lim;
     float L0e, L0f, L0b;  // rest lengths of edge, face-diagonal, body-diagonal springs
-    int32_t gravity, ground, actuation;
+    // Table II contact terms: static friction threshold factor (mu_static k_ground
+    // dt / m), ground damper c_g and the friction factors per unit normal force
+    // (mu dt / m, mu_static dt / m) used when the damper is on
+    float mus_kc_dt_m, cg, mu_dt_m, mus_dt_m;
+    int32_t gravity, ground, actuation, gdamp, dash;
 };
 
 SimConst make_sim_const(const sr_sim_params &p);
@@ -101,9 +106,9 @@ hipError_t launch_adj_springs(const RobotInfo *robots, int total_slots, const in
                               const int64_t *spring_off, Planes pl, float voxel_len, const float *gk, const float *gs,
                               const float *gc, float *g_k, float *g_a, float *g_phi, hipStream_t st);
 hipError_t launch_adj_genome(const RobotInfo *robots, int R, int total_vox, const int32_t *vox_robot,
-                             const uint8_t *kept, Planes pl, const float *gk, const float *gs,
-                             const sr_sim_params &p, const float *genomes, const float *B, float *dJdw, float *g_gen,
-                             hipStream_t st);
+                             const uint8_t *kept, const float *w, Planes pl, const float *gk, const float *gs,
+                             const float *gc, const sr_sim_params &p, const float *genomes, const float *B, float *dJdw,
+                             float *g_gen, hipStream_t st);
 hipError_t launch_advance(int64_t *d_step, int n, hipStream_t st);
 
 hipError_t launch_plain_step(const RobotInfo *robots, int R, int total_slots, const NodeRow *rows,
@@ -116,12 +121,12 @@ hipError_t launch_check_div(const RobotInfo *robots, int R, const float4 *x, con
 
 // persistent LDS-resident kernel for robots of side n; `list` holds the robot
 // ids to step (all of side n).  variant: 0 recompute, 1 exchange, 2 exchange
-// in two direction chunks.
+// in two direction chunks (+4 fences, +8 12-byte loads, +16 spring dashpots).
 struct PersistCfg {
     int n, block, variant;
 };
 bool persist_supported(const PersistCfg &cfg, bool phase);
-int persist_default_block(int n, int *variant);
+int persist_default_block(int n, bool dash, int *variant);
 int persist_list(int n, int32_t *blocks, int32_t *variants, int cap);
 size_t persist_lds_bytes(const PersistCfg &cfg);
 hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo *robots, const int32_t *list,

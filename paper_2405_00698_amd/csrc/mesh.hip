@@ -29,6 +29,9 @@ struct BuildArgs {
     Entry *entries;
     uint8_t *bad_class, *diverged;
     float k_class[5], ac_cos[5], ac_sin[5];
+    float a_class[5], phi_class[5];  // for weight-scaled actuation
+    int weight_act;
+    float dash2m;  // 2 m zeta_spring^2: a voxel spring's dashpot is sqrt(dash2m k_c w)
     float voxel_len;
 };
 
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(BT) void k_build_mesh(BuildArgs A) {
         unsigned mask = 0;
         for (int d = 0; d < NDIR; ++d) {
             const int dx = dir_dx(d), dy = dir_dy(d), dz = dir_dz(d);
-            float ks = 0.f, zr = 0.f, zi = 0.f;
+            float ks = 0.f, zr = 0.f, zi = 0.f, cd = 0.f;
             int hits = 0;
             const int a2 = a + dx, b2 = b + dy, c2 = c + dz;
             if (nid[s] >= 0 && a2 >= 0 && a2 < N && b2 >= 0 && b2 < N && c2 < N) {
@@ -179,10 +182,19 @@ __global__ __launch_bounds__(BT) void k_build_mesh(BuildArgs A) {
                             if (vx < 0 || vx >= n || vy < 0 || vy >= n || vz < 0 || vz >= n) continue;
                             const int kc = lab[vx + n * (vy + n * vz)];
                             if (!kc) continue;
-                            const float kw = A.k_class[kc] * A.w[ri.vox_base + vx + n * (vy + n * vz)];
+                            const float wv = A.w[ri.vox_base + vx + n * (vy + n * vz)];
+                            const float kw = A.k_class[kc] * wv;
                             ks += kw;
-                            zr += kw * A.ac_cos[kc];
-                            zi += kw * A.ac_sin[kc];
+                            if (A.weight_act) {
+                                // amplitude w a_c and phase w phi_c (Table II maxima times the weight)
+                                const float amp = wv * A.a_class[kc], ph = wv * A.phi_class[kc];
+                                zr += kw * (amp * cosf(ph));
+                                zi += kw * (amp * sinf(ph));
+                            } else {
+                                zr += kw * A.ac_cos[kc];
+                                zi += kw * A.ac_sin[kc];
+                            }
+                            cd += sqrtf(A.dash2m * kw);
                             ++hits;
                         }
             }
@@ -194,6 +206,7 @@ __global__ __launch_bounds__(BT) void k_build_mesh(BuildArgs A) {
             A.pl.kL0[pi] = hits ? ks * L0 : 0.f;
             A.pl.kal[pi] = hits ? zr * L0 : 0.f;
             A.pl.kbe[pi] = hits ? zi * L0 : 0.f;
+            A.pl.kd[pi] = hits ? cd : 0.f;
         }
         emask[s] = (uint16_t)mask;
     }
@@ -316,7 +329,11 @@ hipError_t launch_build_mesh(const RobotInfo *robots, int R, int max_side, const
         A.k_class[c] = p.k_class[c];
         A.ac_cos[c] = (float)((double)p.a_class[c] * cos((double)p.phi_class[c]));
         A.ac_sin[c] = (float)((double)p.a_class[c] * sin((double)p.phi_class[c]));
+        A.a_class[c] = p.a_class[c];
+        A.phi_class[c] = p.phi_class[c];
     }
+    A.weight_act = (p.flags & SR_WEIGHT_ACTUATION) != 0;
+    A.dash2m = (float)(2.0 * (double)p.mass * (double)p.zeta_spring * (double)p.zeta_spring);
     A.voxel_len = p.voxel_len;
     hipLaunchKernelGGL(k_build_mesh, dim3(R), dim3(BT), 0, st, A);
     return hipGetLastError();

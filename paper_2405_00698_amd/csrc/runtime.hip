@@ -69,6 +69,7 @@ struct sr_pop {
     bool counts_valid = false;
     bool built = false;
     bool phase = false;
+    bool dash = false;  // spring dashpots: only the +16 persistent kernels
     int mode = SR_STEP_AUTO, spl = 0;
     int sticky = 0;
     // genome query scratch
@@ -128,7 +129,7 @@ void pop_free(sr_pop *pop) {
     for (auto s : pop->side) (void)hipStreamDestroy(s);
     for (auto e : pop->ev) (void)hipEventDestroy(e);
     if (pop->cap) (void)hipStreamDestroy(pop->cap);
-    void *ptrs[] = {pop->d_robots, pop->kept, pop->w, pop->pl.k, pop->pl.kL0, pop->pl.kal, pop->pl.kbe,
+    void *ptrs[] = {pop->d_robots, pop->kept, pop->w, pop->pl.k, pop->pl.kL0, pop->pl.kal, pop->pl.kbe, pop->pl.kd,
                     pop->sid, pop->x0, pop->xbuf[0], pop->xbuf[1], pop->vbuf[0], pop->vbuf[1],
                     pop->slot_node, pop->node_slot, pop->slot_robot, pop->rows, pop->entries,
                     pop->bad_class, pop->diverged, pop->d_step, pop->sc, pop->d_lists, pop->d_mass_off,
@@ -262,12 +263,35 @@ int sr_default_params(sr_sim_params *out) {
     return SR_OK;
 }
 
+int sr_table2_params(sr_sim_params *out) {
+    if (!out) return set_err(SR_EINVAL, "null output");
+    sr_default_params(out);
+    out->dt = 1e-5;
+    out->damping = 1.0f;
+    out->mu = 1.0f;
+    out->mu_static = 0.6f;
+    out->zeta_spring = 0.1f;
+    out->zeta_ground = 0.1f;
+    const float kc[5] = {0.f, 2e3f, 2e3f, 1e3f, 1e4f};
+    const float ac[5] = {0.f, 0.25f, -0.25f, 0.f, 0.f};
+    const float pc[5] = {0.f, (float)M_PI, (float)M_PI, 0.f, 0.f};
+    for (int c = 0; c < 5; ++c) {
+        out->k_class[c] = kc[c];
+        out->a_class[c] = ac[c];
+        out->phi_class[c] = pc[c];
+    }
+    out->flags = SR_WEIGHT_ACTUATION;
+    return SR_OK;
+}
+
 int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *grid_side, void *stream, sr_pop **out) {
     if (!params || !grid_side || !out) return set_err(SR_EINVAL, "null argument");
     *out = nullptr;
     if (n_robots < 1) return set_err(SR_EINVAL, "n_robots must be >= 1 (got %d)", n_robots);
     if (!(params->dt > 0) || !(params->mass > 0) || !(params->voxel_len > 0))
         return set_err(SR_EINVAL, "dt, mass and voxel_len must be positive");
+    if (!(params->mu_static >= 0) || !(params->zeta_spring >= 0) || !(params->zeta_ground >= 0))
+        return set_err(SR_EINVAL, "mu_static, zeta_spring and zeta_ground must be >= 0");
     for (int r = 0; r < n_robots; ++r)
         if (grid_side[r] < 1 || grid_side[r] > SR_MAX_SIDE)
             return set_err(SR_EINVAL, "grid_side[%d] = %d outside 1..%d", r, grid_side[r], SR_MAX_SIDE);
@@ -300,6 +324,7 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
     }
     for (int c = 0; c < 5; ++c)
         if (params->phi_class[c] != 0.f) pop->phase = true;
+    pop->dash = params->zeta_spring != 0.f;
     pop->total_slots = (int)slots;
     pop->total_vox = (int)vox;
     const size_t S = slots, P = slots * NDIR;
@@ -313,6 +338,7 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
     ALLOC(pop->pl.kL0, P);
     ALLOC(pop->pl.kal, P);
     ALLOC(pop->pl.kbe, P);
+    ALLOC(pop->pl.kd, P);
     ALLOC(pop->sid, P);
     ALLOC(pop->x0, S);
     ALLOC(pop->xbuf[0], S);
@@ -353,7 +379,7 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
         g.offset = (int)lists.size();
         g.count = (int)kv.second.size();
         g.cfg.n = kv.first;
-        g.cfg.block = persist_default_block(kv.first, &g.cfg.variant);
+        g.cfg.block = persist_default_block(kv.first, pop->dash, &g.cfg.variant);
         lists.insert(lists.end(), kv.second.begin(), kv.second.end());
         pop->groups.push_back(g);
     }
@@ -432,7 +458,7 @@ int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_
         for (auto &g : pop->groups) {
             bool found = false;
             for (int var : {1, 5, 2, 6, 0, 4}) {
-                PersistCfg c{g.n, block, var};
+                PersistCfg c{g.n, block, var + (pop->dash ? 16 : 0)};
                 if (persist_supported(c, pop->phase)) {
                     g.cfg = c;
                     found = true;
@@ -452,6 +478,9 @@ int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t varia
             PersistCfg c{n, block, variant};
             if (!persist_supported(c, pop->phase))
                 return set_err(SR_EUNSUPPORTED, "no persistent kernel for n=%d block=%d variant=%d", n, block, variant);
+            if (((variant & 16) != 0) != pop->dash)
+                return set_err(SR_EUNSUPPORTED, "variant %d %s spring dashpots; this population has %s", variant,
+                               (variant & 16) ? "has" : "lacks", pop->dash ? "them" : "none");
             g.cfg = c;
             clear_graphs(pop);
             return SR_OK;
@@ -739,6 +768,8 @@ int pop_record(sr_pop *pop, int32_t checkpoint_every, int32_t max_steps) {
     pop->ck_cap = 0;
     pop->rec_valid = false;
     if (checkpoint_every == 0) return SR_OK;
+    if (pop->p.zeta_spring != 0.f || pop->p.zeta_ground != 0.f)
+        return set_err(SR_EUNSUPPORTED, "no adjoint with spring or ground dashpots");
     const int cap = max_steps / checkpoint_every + 1;
     hipError_t e = dalloc(&pop->ck_x, (size_t)cap * pop->total_slots);
     if (e == hipSuccess) e = dalloc(&pop->ck_v, (size_t)cap * pop->total_slots);
@@ -786,10 +817,8 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     if (!pop->rec_valid || pop->ck_every <= 0)
         return set_err(SR_ESTATE, "no recorded run: call pop_record right after the build, then pop_step");
     if (g_genome && (!genomes || !B)) return set_err(SR_EINVAL, "genome gradient needs the genomes and B");
-    if (g_genome)
-        for (int c = 0; c < 5; ++c)
-            if (pop->p.phi_class[c] != 0.f)
-                return set_err(SR_EUNSUPPORTED, "genome gradient needs every class phase to be zero");
+    if (pop->p.zeta_spring != 0.f || pop->p.zeta_ground != 0.f)
+        return set_err(SR_EUNSUPPORTED, "no adjoint with spring or ground dashpots");
     for (const auto &gr : pop->groups)
         if (gr.n > 11) return set_err(SR_EUNSUPPORTED, "no adjoint kernel for side %d", gr.n);
     const int K = pop->ck_every;
@@ -823,8 +852,8 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     HIPC(pop, launch_adj_springs(pop->d_robots, pop->total_slots, pop->slot_robot, pop->sid, pop->d_spring_off, pop->pl,
                                  pop->p.voxel_len, pop->gk, pop->gs, pop->gc, g_k, g_a, g_phi, pop->st));
     if (g_genome)
-        HIPC(pop, launch_adj_genome(pop->d_robots, pop->R, pop->total_vox, pop->vox_robot, pop->kept, pop->pl, pop->gk,
-                                    pop->gs, pop->p, genomes, B, pop->dJdw, g_genome, pop->st));
+        HIPC(pop, launch_adj_genome(pop->d_robots, pop->R, pop->total_vox, pop->vox_robot, pop->kept, pop->w, pop->pl,
+                                    pop->gk, pop->gs, pop->gc, pop->p, genomes, B, pop->dJdw, g_genome, pop->st));
     return SR_OK;
 }
 

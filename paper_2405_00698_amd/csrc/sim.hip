@@ -16,9 +16,15 @@ SimConst make_sim_const(const sr_sim_params &p) {
     c.L0e = p.voxel_len * sqrtf(1.0f);
     c.L0f = p.voxel_len * sqrtf(2.0f);
     c.L0b = p.voxel_len * sqrtf(3.0f);
+    c.mus_kc_dt_m = (float)((double)p.mu_static * (double)p.k_ground * p.dt / (double)p.mass);
+    c.cg = (float)(2.0 * (double)p.zeta_ground * sqrt((double)p.k_ground * (double)p.mass));
+    c.mu_dt_m = (float)((double)p.mu * p.dt / (double)p.mass);
+    c.mus_dt_m = (float)((double)p.mu_static * p.dt / (double)p.mass);
     c.gravity = !(p.flags & SR_NO_GRAVITY);
     c.ground = !(p.flags & SR_NO_GROUND);
     c.actuation = !(p.flags & SR_NO_ACTUATION);
+    c.gdamp = p.zeta_ground != 0.f;
+    c.dash = p.zeta_spring != 0.f;
     return c;
 }
 
@@ -60,8 +66,9 @@ __global__ void k_advance(int64_t *d_step, int n) {
 // ---------------------------------------------------------------- per-step form
 // One thread per node; positions and velocities in HBM, one launch per step.
 // The node gathers over its incidence row (forward springs, then backward
-// springs), recomputing every spring force it touches.
-template <bool PHASE>
+// springs), recomputing every spring force it touches.  DASH adds the spring
+// dashpots (neighbour velocities read from HBM too).
+template <bool PHASE, bool DASH>
 __global__ __launch_bounds__(256) void k_plain(const RobotInfo *robots, int total_slots, const int32_t *slot_robot,
                                                const NodeRow *rows, const Entry *entries, Planes pl,
                                                const float4 *__restrict__ x, const float4 *__restrict__ v,
@@ -75,13 +82,22 @@ __global__ __launch_bounds__(256) void k_plain(const RobotInfo *robots, int tota
     if (g - ri.slot_base >= ri.M || diverged[r]) return;
     const NodeRow row = rows[g];
     const float4 X = x[row.gslot];
+    const float4 V = v[row.gslot];
     float3 Ff = make_float3(0.f, 0.f, 0.f), Fb = make_float3(0.f, 0.f, 0.f);
     for (int e = row.start; e < row.mid; ++e) {
         const Entry E = entries[e];
         const float4 Y = x[E.nbr];
         const float dx = Y.x - X.x, dy = Y.y - X.y, dz = Y.z - X.z;
-        const float cf = spring_coef<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane],
-                                            PHASE ? pl.kbe[E.plane] : 0.f, sc.x, sc.y, len2(dx, dy, dz));
+        float cf;
+        if constexpr (DASH) {
+            const float4 VY = v[E.nbr];
+            cf = spring_coef_d<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane], PHASE ? pl.kbe[E.plane] : 0.f,
+                                      sc.x, sc.y, len2(dx, dy, dz), pl.kd[E.plane],
+                                      rate(VY.x - V.x, VY.y - V.y, VY.z - V.z, dx, dy, dz));
+        } else {
+            cf = spring_coef<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane], PHASE ? pl.kbe[E.plane] : 0.f,
+                                    sc.x, sc.y, len2(dx, dy, dz));
+        }
         Ff.x = fmaf(cf, dx, Ff.x);
         Ff.y = fmaf(cf, dy, Ff.y);
         Ff.z = fmaf(cf, dz, Ff.z);
@@ -90,14 +106,21 @@ __global__ __launch_bounds__(256) void k_plain(const RobotInfo *robots, int tota
         const Entry E = entries[e];
         const float4 Y = x[E.nbr];
         const float dx = Y.x - X.x, dy = Y.y - X.y, dz = Y.z - X.z;
-        const float cf = spring_coef<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane],
-                                            PHASE ? pl.kbe[E.plane] : 0.f, sc.x, sc.y, len2(dx, dy, dz));
+        float cf;
+        if constexpr (DASH) {
+            const float4 VY = v[E.nbr];
+            cf = spring_coef_d<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane], PHASE ? pl.kbe[E.plane] : 0.f,
+                                      sc.x, sc.y, len2(dx, dy, dz), pl.kd[E.plane],
+                                      rate(VY.x - V.x, VY.y - V.y, VY.z - V.z, dx, dy, dz));
+        } else {
+            cf = spring_coef<PHASE>(pl.k[E.plane], pl.kL0[E.plane], pl.kal[E.plane], PHASE ? pl.kbe[E.plane] : 0.f,
+                                    sc.x, sc.y, len2(dx, dy, dz));
+        }
         Fb.x = fmaf(cf, dx, Fb.x);
         Fb.y = fmaf(cf, dy, Fb.y);
         Fb.z = fmaf(cf, dz, Fb.z);
     }
     float3 xs = make_float3(X.x, X.y, X.z);
-    const float4 V = v[row.gslot];
     float3 vs = make_float3(V.x, V.y, V.z);
     integrate_node(c, xs, vs, Ff, Fb);
     xn[row.gslot] = make_float4(xs.x, xs.y, xs.z, 1.f);
@@ -138,6 +161,12 @@ __global__ __launch_bounds__(256) void k_check_div(const RobotInfo *robots, cons
 //    itself from the lower slot's parameters (held in its own VGPRs).
 // All variants produce identical bits: each coefficient is computed from the
 // same operands with the same operations.
+//
+// DASH (spring dashpots, Table II model): velocities are mirrored into one LDS
+// buffer so a spring can read both endpoint velocities.  It is written in the
+// node update, after the barrier that ends every read of the step (the
+// recompute variant gets that extra barrier), and read after the end-of-step
+// barrier.
 struct PArgs {
     const RobotInfo *robots;
     const int32_t *list;
@@ -153,14 +182,14 @@ struct PArgs {
     float4 *rec_x, *rec_v;
 };
 
-template <int N, int BS, int VAR>
+template <int N, int BS, int VAR, bool DASH = false>
 constexpr size_t lds_bytes() {
     using G = Geo<N>;
     constexpr int NDC = VAR == 0 ? 0 : (NDIR + VAR - 1) / VAR;
-    return 2 * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL;
+    return (DASH ? 3 : 2) * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL;
 }
 
-template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true>
+template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
@@ -174,6 +203,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     __shared__ float4 xb0[XL];
     __shared__ float4 xb1[XL];
     __shared__ float coef[NDC > 0 ? NDC * CL : 1];
+    __shared__ float4 vb[DASH ? XL : 1];
     __shared__ int bad;
     const int tid = threadIdx.x;
     const SimConst c = A.c;
@@ -193,6 +223,10 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
             xb1[i] = ghost;
             xb0[PAD + SL + i] = ghost;
             xb1[PAD + SL + i] = ghost;
+            if constexpr (DASH) {
+                vb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                vb[PAD + SL + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
         if (tid == 0) bad = 0;
 
@@ -200,6 +234,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
         bool pres[NPT];
         float pk[NPT][NDIR], pa[NPT][NDIR], pb[NPT][NB];
         float qk[NPT][NQ], qa[NPT][NQ], qb[NPT][NQ];
+        float pd[NPT][DASH ? NDIR : 1], qd[NPT][DASH ? NQ : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int s = tid + k * BS;
@@ -210,6 +245,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
             if (live) {
                 xb0[PAD + s] = X;
                 xb1[PAD + s] = X;
+                if constexpr (DASH) vb[PAD + s] = V;
             }
             xr[k] = make_float3(X.x, X.y, X.z);
             vr[k] = make_float3(V.x, V.y, V.z);
@@ -220,6 +256,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 pk[k][d] = live ? A.pl.k[pi] : 0.f;
                 pa[k][d] = live ? A.pl.kal[pi] : 0.f;
                 if (PHASE) pb[k][d] = live ? A.pl.kbe[pi] : 0.f;
+                if constexpr (DASH) pd[k][d] = live ? A.pl.kd[pi] : 0.f;
             }
             if (VAR == 0) {
 #pragma unroll
@@ -230,6 +267,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     qk[k][d] = ok ? A.pl.k[pi] : 0.f;
                     qa[k][d] = ok ? A.pl.kal[pi] : 0.f;
                     qb[k][d] = (ok && PHASE) ? A.pl.kbe[pi] : 0.f;
+                    if constexpr (DASH) qd[k][d] = ok ? A.pl.kd[pi] : 0.f;
                 }
             }
         }
@@ -256,8 +294,17 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         for (int d = 0; d < NDIR; ++d) {
                             const float3 Y = ldx<WIDE>(xc + s + (PAD + dir_off(d, N)));
                             const float dx = Y.x - xr[k].x, dy = Y.y - xr[k].y, dz = Y.z - xr[k].z;
-                            const float cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
-                                                                PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz));
+                            float cf;
+                            if constexpr (DASH) {
+                                const float3 VY = ldx<WIDE>(vb + s + (PAD + dir_off(d, N)));
+                                cf = spring_coef_d<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
+                                                          PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz),
+                                                          pd[k][d],
+                                                          rate(VY.x - vr[k].x, VY.y - vr[k].y, VY.z - vr[k].z, dx, dy, dz));
+                            } else {
+                                cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
+                                                        PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz));
+                            }
                             Ff[k].x = fmaf(cf, dx, Ff[k].x);
                             Ff[k].y = fmaf(cf, dy, Ff[k].y);
                             Ff[k].z = fmaf(cf, dz, Ff[k].z);
@@ -266,8 +313,16 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         for (int d = 0; d < NQ; ++d) {
                             const float3 Y = ldx<WIDE>(xc + s + (PAD - dir_off(d, N)));
                             const float ex = Y.x - xr[k].x, ey = Y.y - xr[k].y, ez = Y.z - xr[k].z;
-                            const float cf = spring_coef<PHASE>(qk[k][d], qk[k][d] * L0d(c, d), qa[k][d], qb[k][d],
-                                                                sct.x, sct.y, len2(ex, ey, ez));
+                            float cf;
+                            if constexpr (DASH) {
+                                const float3 VY = ldx<WIDE>(vb + s + (PAD - dir_off(d, N)));
+                                cf = spring_coef_d<PHASE>(qk[k][d], qk[k][d] * L0d(c, d), qa[k][d], qb[k][d], sct.x,
+                                                          sct.y, len2(ex, ey, ez), qd[k][d],
+                                                          rate(VY.x - vr[k].x, VY.y - vr[k].y, VY.z - vr[k].z, ex, ey, ez));
+                            } else {
+                                cf = spring_coef<PHASE>(qk[k][d], qk[k][d] * L0d(c, d), qa[k][d], qb[k][d], sct.x,
+                                                        sct.y, len2(ex, ey, ez));
+                            }
                             Fb[k].x = fmaf(cf, ex, Fb[k].x);
                             Fb[k].y = fmaf(cf, ey, Fb[k].y);
                             Fb[k].z = fmaf(cf, ez, Fb[k].z);
@@ -287,16 +342,28 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             // addresses are one base plus non-negative immediates
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
-                            float3 Y[NDIR];
+                            float3 Y[NDIR], VY[DASH ? NDIR : 1];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) Y[d] = ldx<WIDE>(xs + (PAD + dir_off(d, N)));
+                            if constexpr (DASH) {
+#pragma unroll
+                                for (int d = d0; d < d1; ++d) VY[DASH ? d : 0] = ldx<WIDE>(vb + s + (PAD + dir_off(d, N)));
+                            }
                             float cfv[NDIR];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
                                 const float dx = Y[d].x - xr[k].x, dy = Y[d].y - xr[k].y, dz = Y[d].z - xr[k].z;
-                                const float cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
-                                                                    PHASE ? pb[k][d] : 0.f, sct.x, sct.y,
-                                                                    len2(dx, dy, dz));
+                                float cf;
+                                if constexpr (DASH) {
+                                    const float3 W = VY[DASH ? d : 0];
+                                    cf = spring_coef_d<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
+                                                              PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz),
+                                                              pd[k][DASH ? d : 0],
+                                                              rate(W.x - vr[k].x, W.y - vr[k].y, W.z - vr[k].z, dx, dy, dz));
+                                } else {
+                                    cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
+                                                            PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz));
+                                }
                                 cfv[d] = cf;
                                 Ff[k].x = fmaf(cf, dx, Ff[k].x);
                                 Ff[k].y = fmaf(cf, dy, Ff[k].y);
@@ -334,6 +401,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     if (ch + 1 < NCH) __syncthreads();
                 }
             }
+            if constexpr (DASH && VAR == 0) __syncthreads();  // every velocity read of the step is done
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int s = tid + k * BS;
@@ -343,6 +411,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     integrate_node(c, xr[k], vr[k], Ff[k], Fb[k], REC ? &vp : nullptr);
                     if (REC) A.rec_v[(size_t)A.n_steps * base + (size_t)t * SL + s] = make_float4(vp.x, vp.y, vp.z, 0.f);
                     xn[PAD + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
+                    if constexpr (DASH) vb[PAD + s] = make_float4(vr[k].x, vr[k].y, vr[k].z, 0.f);
                 }
             }
             __syncthreads();
@@ -478,10 +547,18 @@ struct PersistEntry {
 
 // variant code: exchange variant (0, 1, 2) + 4 when scheduling fences bound the
 // number of LDS loads in flight + 8 for 12-byte instead of 16-byte position loads
+// + 16 for the spring-dashpot kernels
 #define SR_PE(NN, BS, VAR, F, W)                                                                        \
     {                                                                                                   \
         NN, BS, VAR + 4 * F + 8 * (1 - W), k_persist<NN + 1, BS, VAR, F, false, false, W>,              \
             k_persist<NN + 1, BS, VAR, F, true, false, W>, lds_bytes<NN + 1, BS, VAR>()                 \
+    }
+// dashpot kernels carry the phase plane always (with a zero plane the results
+// are the same bits as without it)
+#define SR_PD(NN, BS, VAR)                                                                              \
+    {                                                                                                   \
+        NN, BS, VAR + 16, k_persist<NN + 1, BS, VAR, false, true, false, true, true>,                   \
+            k_persist<NN + 1, BS, VAR, false, true, false, true, true>, lds_bytes<NN + 1, BS, VAR, true>() \
     }
 
 // The first entry of each side is its default configuration.
@@ -496,6 +573,12 @@ const PersistEntry kPersist[] = {
     SR_PE(10, 448, 2, 0, 1),  SR_PE(10, 448, 0, 0, 1),  SR_PE(10, 512, 0, 0, 1),  SR_PE(10, 384, 1, 0, 1), SR_PE(11, 896, 1, 0, 1),
     SR_PE(11, 896, 1, 1, 1),  SR_PE(11, 576, 1, 0, 1),  SR_PE(11, 576, 1, 1, 1),  SR_PE(11, 1024, 0, 0, 1), SR_PE(12, 768, 2, 0, 1),
     SR_PE(12, 768, 2, 1, 1),  SR_PE(12, 768, 0, 0, 1),  SR_PE(12, 1024, 2, 0, 1), SR_PE(12, 1024, 2, 1, 1),
+    // spring dashpots (Table II model)
+    SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
+    SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
+    SR_PD(7, 512, 0),   SR_PD(8, 768, 1),   SR_PD(8, 768, 0),    SR_PD(9, 512, 1),   SR_PD(9, 1024, 1),
+    SR_PD(9, 512, 0),   SR_PD(10, 512, 1),  SR_PD(10, 448, 1),   SR_PD(10, 704, 1),  SR_PD(11, 512, 2),
+    SR_PD(11, 576, 2),  SR_PD(11, 896, 2),  SR_PD(12, 512, 0),   SR_PD(12, 768, 0),
 };
 
 #define SR_REC(NN, BS, VAR) \
@@ -539,9 +622,9 @@ int persist_list(int n, int32_t *blocks, int32_t *variants, int cap) {
     return cnt;
 }
 
-int persist_default_block(int n, int *variant) {
+int persist_default_block(int n, bool dash, int *variant) {
     for (const auto &e : kPersist)
-        if (e.n == n && e.lds <= 160 * 1024) {
+        if (e.n == n && e.lds <= 160 * 1024 && ((e.variant & 16) != 0) == dash) {
             *variant = e.variant;
             return e.block;
         }
@@ -617,12 +700,10 @@ hipError_t launch_plain_step(const RobotInfo *robots, int R, int total_slots, co
                              int t, bool phase, const uint8_t *diverged, const int32_t *slot_robot, SimConst c,
                              hipStream_t st) {
     (void)R;
-    if (phase)
-        hipLaunchKernelGGL(k_plain<true>, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots,
-                           slot_robot, rows, entries, pl, x, v, xn, vn, sc, t, diverged, c);
-    else
-        hipLaunchKernelGGL(k_plain<false>, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots,
-                           slot_robot, rows, entries, pl, x, v, xn, vn, sc, t, diverged, c);
+    auto fn = c.dash ? (phase ? k_plain<true, true> : k_plain<false, true>)
+                     : (phase ? k_plain<true, false> : k_plain<false, false>);
+    hipLaunchKernelGGL(fn, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots, slot_robot, rows,
+                       entries, pl, x, v, xn, vn, sc, t, diverged, c);
     return hipGetLastError();
 }
 

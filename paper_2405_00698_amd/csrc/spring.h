@@ -34,6 +34,23 @@ __device__ __forceinline__ float spring_coef(float k, float kL0, float kal, floa
     return fmaf(-kL, ir, k);
 }
 
+// The same with a dashpot of coefficient kd beside the spring: the force on
+// the lower endpoint gains kd ((v_upper - v_lower).d / r) d / r, i.e. the
+// coefficient of d gains kd vr / r^2 with vr = (v_upper - v_lower).d.  Swapping
+// the endpoints negates both differences, so either end gets the same bits.
+template <bool PHASE>
+__device__ __forceinline__ float spring_coef_d(float k, float kL0, float kal, float kbe, float S, float C, float r2,
+                                               float kd, float vr) {
+    float kL = fmaf(kal, S, kL0);
+    if (PHASE) kL = fmaf(kbe, C, kL);
+    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+    return fmaf(kd * vr, ir * ir, fmaf(-kL, ir, k));
+}
+
+__device__ __forceinline__ float rate(float dvx, float dvy, float dvz, float dx, float dy, float dz) {
+    return fmaf(dvz, dz, fmaf(dvy, dy, dvx * dx));
+}
+
 // rest length of direction d: voxel edge times 1, sqrt 2 or sqrt 3
 __device__ __forceinline__ float L0d(const SimConst &c, int d) {
     return dir_len2(d) == 1 ? c.L0e : dir_len2(d) == 2 ? c.L0f : c.L0b;
@@ -63,20 +80,31 @@ __device__ __forceinline__ float3 ldx(const float4 *p) {
 __device__ __forceinline__ float len2(float dx, float dy, float dz) { return fmaf(dz, dz, fmaf(dy, dy, dx * dx)); }
 
 // One node's update from its total spring force (forward-direction sum Ff and
-// backward-direction sum Fb, added in that order): gravity, ground normal,
-// semi-implicit Euler, velocity-level Coulomb friction, damping.
+// backward-direction sum Fb, added in that order): gravity, ground normal
+// (with the Table II contact damper, clamped at zero, when c.gdamp), semi-
+// implicit Euler, velocity-level Coulomb friction (sticking within the larger
+// of the static and kinetic thresholds), damping.
 __device__ __forceinline__ void integrate_node(const SimConst &c, float3 &x, float3 &v, float3 Ff, float3 Fb,
                                                float3 *vprime = nullptr) {
     float Fx = Ff.x + Fb.x, Fy = Ff.y + Fb.y, Fz = Ff.z + Fb.z;
     const bool below = c.ground && x.z < 0.f;
     if (c.gravity) Fz -= c.mg;
-    if (below) Fz = fmaf(c.kc, -x.z, Fz);
+    float Nf = 0.f;
+    if (below) {
+        if (c.gdamp) {
+            Nf = fmaxf(fmaf(-c.cg, v.z, c.kc * -x.z), 0.f);
+            Fz += Nf;
+        } else {
+            Fz = fmaf(c.kc, -x.z, Fz);
+        }
+    }
     float vx = fmaf(c.dt_m, Fx, v.x), vy = fmaf(c.dt_m, Fy, v.y), vz = fmaf(c.dt_m, Fz, v.z);
     if (vprime) *vprime = make_float3(vx, vy, vz);
     if (below) {
-        const float dv = c.mu_kc_dt_m * (-x.z);
+        const float dv = c.gdamp ? c.mu_dt_m * Nf : c.mu_kc_dt_m * (-x.z);
+        const float dvs = c.gdamp ? c.mus_dt_m * Nf : c.mus_kc_dt_m * (-x.z);
         const float u = sqrtf(fmaf(vy, vy, vx * vx));
-        if (u <= dv) {
+        if (u <= fmaxf(dv, dvs)) {
             vx = 0.f;
             vy = 0.f;
         } else {

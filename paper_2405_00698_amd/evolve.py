@@ -60,16 +60,19 @@ def rule_supervisor(history):
 
 
 def evolve(sides, generations=100, sim_steps=10000, seed_genome=1, seed_ga=3, sigma_B=1.0,
-           params=None, supervisor=None, empty_bias=None, log=None, precision=SR_QUERY_BF16, **sim):
+           params=None, supervisor=None, empty_bias=None, log=None, precision=SR_QUERY_BF16,
+           sim_params=None, **sim):
     """Runs `generations` generations on the given grid sides; returns the
-    per-generation history (parameters, fitness statistics, diversity, times)."""
+    per-generation history (parameters, fitness statistics, diversity, times).
+    sim_params: a full sr_sim_params (e.g. table2_params()); else the defaults
+    with the keyword overrides in **sim."""
     dev = torch.device("cuda:0")
     R = len(sides)
     params = dict(elite_frac=0.3, tournament_k=4, p_cross=0.4, p_mut=0.1, sigma=0.02) if params is None else params
     B = torch.from_numpy(inputs.gaussian_B(sigma=sigma_B)).to(dev)
     G = [torch.from_numpy(inputs.random_genomes(R, seed=seed_genome, empty_bias=empty_bias)).to(dev),
          torch.empty((R, inputs.GENOME_LEN), dtype=torch.float32, device=dev)]
-    P = Population(sides, **sim)
+    P = Population(sides, params=sim_params, **sim)
     fit = torch.empty(R, dtype=torch.float32, device=dev)
     history = []
     for g in range(generations):
@@ -123,11 +126,15 @@ if __name__ == "__main__":
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--repeats", type=int, default=1, help="independent runs (genome seeds seed, seed+1, ...)")
     ap.add_argument("--sigma-sweep", default=None, help="comma-separated values of sigma_B to sweep")
+    ap.add_argument("--table2", action="store_true",
+                    help="Table II material and contact model (dt 1e-5 s, weighted muscles, dashpots)")
     a = ap.parse_args()
+    from ._lib import table2_params
+    simp = table2_params() if a.table2 else None
     sup = rule_supervisor if a.supervisor else None
     sigmas = [float(q) for q in a.sigma_sweep.split(",")] if a.sigma_sweep else [a.sigma_B]
     for s in sigmas:
         for r in range(a.repeats):
             sys.stdout.write(json.dumps({"sigma_B": s, "repeat": r}) + "\n")
             evolve([a.side] * a.robots, a.generations, a.sim_steps, seed_genome=a.seed + r, sigma_B=s,
-                   supervisor=sup, log=sys.stdout)
+                   supervisor=sup, log=sys.stdout, sim_params=simp)

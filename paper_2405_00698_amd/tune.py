@@ -30,7 +30,7 @@ def tune(pop, steps=200, cache_path=None, verbose=False):
         counts[n] = counts.get(n, 0) + 1
     result = {}
     for n, cnt in sorted(counts.items()):
-        key = "%s|n=%d|R<=%d" % (dev_name, n, _bucket(cnt))
+        key = "%s|n=%d|R<=%d%s" % (dev_name, n, _bucket(cnt), "|dash" if pop.dashpots else "")
         if key in cache:
             b, v, t = cache[key]
             pop.set_persist_variant(n, b, v)
@@ -38,6 +38,8 @@ def tune(pop, steps=200, cache_path=None, verbose=False):
             continue
         best = None
         for b, v in api.persist_configs(n):
+            if bool(v & 16) != pop.dashpots:
+                continue  # kernels for the other spring model
             pop.set_persist_variant(n, b, v)
             pop.reset()
             pop.step(20)

@@ -98,3 +98,15 @@ def test_codesign_driver_paper_shape_short():
     best = [r["fit_max"] for r in h1]
     assert all(b2 >= b1 for b1, b2 in zip(best, best[1:]))
     say("paper-shape run", [("%.4f" % r["fit_max"], "%.3f" % r["div_morph"]) for r in h1])
+
+
+def test_codesign_driver_table2_model_and_sigma_sweep():
+    """The co-design loop under the Table II model (weighted muscles, dashpots,
+    dt 1e-5 s) and a two-value sweep of the encoding scale sigma_B."""
+    from paper_2405_00698_amd._lib import table2_params
+    from paper_2405_00698_amd.evolve import sigma_sweep
+    res = sigma_sweep([0.5, 2.0], [5] * 30, generations=3, sim_steps=3000, sim_params=table2_params())
+    for s, runs in res.items():
+        best = [r["fit_max"] for r in runs[0]]
+        assert all(np.isfinite(best)) and all(b2 >= b1 for b1, b2 in zip(best, best[1:]))
+        say("sigma_B", s, "best", ["%.5f" % b for b in best], "diversity %.3f" % runs[0][-1]["div_morph"])

@@ -1,0 +1,196 @@
+"""GPU parity of the Table II material and contact model against the FP64
+oracle, through the C ABI: weight-scaled muscle amplitude and phase, spring
+and ground dashpots, static/kinetic friction.  Same bars as the base model:
+spring parameters to FP32 rounding, positions within 1e-3 relative with
+contact, all dashpot kernel configurations bit-identical to the per-step
+kernel, gradients within 1e-2 / 2e-2 relative L2."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DEV, gpu_states, need_gpu, oracle_robots, rel_err, say, voxel_population
+from paper_2405_00698_amd import SR_QUERY_FP32, SR_STEP_PERSISTENT, SR_STEP_PLAIN, SoftRobotError, inputs
+from paper_2405_00698_amd._lib import table2_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _pop(sides, cls, w, **over):
+    from paper_2405_00698_amd.api import Population
+    P = Population(sides, params=table2_params(**over))
+    P.build_from_voxels(torch.from_numpy(cls).to(DEV), torch.from_numpy(w).to(DEV))
+    return P
+
+
+def _oparams(orc, **over):
+    return dict(orc.TABLE2, **over)
+
+
+def test_table2_preset_matches_oracle_preset(orc):
+    p = table2_params()
+    t = orc.TABLE2
+    assert p.dt == t["dt"] and p.flags == t["flags"] and p.damping == t["damping"]
+    for k in ("mu", "mu_static", "zeta_spring", "zeta_ground", "k_ground", "gravity", "mass", "voxel_len"):
+        assert getattr(p, k) == pytest.approx(t[k], rel=1e-7), k
+    for k in ("k_class", "a_class", "phi_class"):
+        np.testing.assert_allclose(list(getattr(p, k)), t[k], rtol=1e-7)
+
+
+def test_weighted_actuation_springs_match_oracle(orc):
+    sides = [1, 2, 3, 4, 5, 8]
+    cls, w = voxel_population(sides, 61, p_empty=0.25)
+    P = _pop(sides, cls, w)
+    robots = oracle_robots(orc, sides, cls, w, **_oparams(orc))
+    M, S, mo, so = P.counts()
+    sp = {k: v.cpu().numpy().astype(np.float64) for k, v in P.springs().items()}
+    for r, R in enumerate(robots):
+        o = R.springs()
+        sl = slice(so[r], so[r + 1])
+        assert np.array_equal(sp["ij"][sl], o["ij"])
+        np.testing.assert_allclose(sp["k"][sl], o["k"], rtol=2e-6)
+        # compare the phasor k a e^{i phi}: the phase of a near-zero amplitude is ill-defined
+        Zg = sp["k"][sl] * sp["a"][sl] * np.exp(1j * sp["phi"][sl])
+        Zo = o["k"] * o["a"] * np.exp(1j * o["phi"])
+        assert np.abs(Zg - Zo).max() <= 1e-5 * max(np.abs(Zo).max(), 1.0)
+
+
+@pytest.mark.parametrize("mode", [SR_STEP_PERSISTENT, SR_STEP_PLAIN])
+def test_table2_step_parity_with_contact(orc, mode):
+    # 2000 steps of 1e-5 s: the robots drop onto the ground, the dashpots and
+    # the ground damper act, the weighted muscles start to move them
+    sides = [2, 3, 4, 5, 6]
+    cls, w = voxel_population(sides, 62)
+    say("table2 step parity mode", mode)
+    P = _pop(sides, cls, w)
+    P.set_step_config(mode)
+    robots = oracle_robots(orc, sides, cls, w, **_oparams(orc))
+    P.step(2000)
+    for R in robots:
+        R.step(2000)
+    xs, vs, st = gpu_states(P)
+    fit = P.fitness().cpu().numpy()
+    for r, R in enumerate(robots):
+        x, v, _, dv = R.state()
+        assert not dv
+        e = rel_err(xs[r], x)
+        say("robot", r, "side", sides[r], "rel err %.2e" % e)
+        assert e <= 1e-3
+        assert abs(fit[r] - R.fitness()) <= 1e-3 * np.abs(x).max()
+        assert x[:, 2].min() < 0  # in contact
+
+
+def test_table2_contact_and_friction_exercised(orc):
+    # longer run of the paper's robot size with the muscles on (0.02 s)
+    sides = [5] * 4
+    cls, w = voxel_population(sides, 63)
+    P = _pop(sides, cls, w)
+    robots = oracle_robots(orc, sides, cls, w, **_oparams(orc))
+    P.step(2000)
+    for R in robots:
+        R.step(2000)
+    xs, vs, _ = gpu_states(P)
+    for r, R in enumerate(robots):
+        x, v, _, _ = R.state()
+        assert rel_err(xs[r], x) <= 1e-3
+        np.testing.assert_allclose(vs[r], v, atol=1e-3 * max(np.abs(v).max(), 1e-3))
+
+
+@pytest.mark.parametrize("n", [3, 5, 8, 9, 10, 11, 12])
+def test_dashpot_kernels_bitwise_equal_per_step_kernel(n):
+    from paper_2405_00698_amd import api
+    sides = [n] * 3
+    cls, w = voxel_population(sides, 64)
+    ref = _pop(sides, cls, w)
+    ref.set_step_config(SR_STEP_PLAIN)
+    ref.step(120)
+    xr, vr, _ = ref.state()
+    configs = [(b, v) for b, v in api.persist_configs(n) if v & 16]
+    assert configs
+    for b, v in configs:
+        say("dashpot kernel", n, b, v)
+        P = _pop(sides, cls, w)
+        P.set_persist_variant(n, b, v)
+        P.step(120)
+        x, vv, _ = P.state()
+        assert torch.equal(x, xr) and torch.equal(vv, vr), (b, v)
+
+
+def test_kernel_kind_must_match_model():
+    from paper_2405_00698_amd.api import Population
+    sides = [5] * 2
+    cls, w = voxel_population(sides, 65)
+    P = _pop(sides, cls, w)
+    assert P.persist_variant(5)[1] & 16
+    with pytest.raises(SoftRobotError):
+        P.set_persist_variant(5, 256, 1)          # a kernel without dashpots
+    Q = Population(sides)
+    with pytest.raises(SoftRobotError):
+        Q.set_persist_variant(5, 256, 17)         # a dashpot kernel for the base model
+
+
+def test_no_adjoint_with_dashpots():
+    sides = [3] * 2
+    cls, w = voxel_population(sides, 66)
+    P = _pop(sides, cls, w)
+    with pytest.raises(SoftRobotError):
+        P.record(10, 100)
+
+
+def test_static_friction_step_and_adjoint(orc):
+    # base model with static friction above kinetic (0.8 vs 0.5)
+    from gpu_util import gpu_population
+    sides = [4] * 6
+    cls, w = voxel_population(sides, 67)
+    P = gpu_population(sides, cls, w, mu_static=0.8)
+    robots = oracle_robots(orc, sides, cls, w, mu_static=0.8)
+    steps, K = 200, 50
+    P.record(K, steps)
+    P.step(steps)
+    xs, _, _ = gpu_states(P)
+    dJ = np.random.default_rng(4).uniform(0.5, 1.5, size=len(sides)).astype(np.float32)
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in P.backward(torch.from_numpy(dJ).to(DEV)).items()}
+    M, S, mo, so = P.counts()
+    for r, R in enumerate(robots):
+        J, gk, ga, gp = R.backward(steps, g=float(dJ[r]))
+        R.step(steps)
+        assert rel_err(xs[r], R.state()[0]) <= 1e-3
+        sl = slice(so[r], so[r + 1])
+        for key, ref in (("k", gk), ("a", ga)):
+            e = float(np.linalg.norm(g[key][sl] - ref) / max(np.linalg.norm(ref), 1e-300))
+            assert e < 1e-2, (r, key, e)
+
+
+def test_genome_gradient_weighted_actuation(orc):
+    # weight-scaled amplitude and phase (Table II model without the dashpots)
+    from paper_2405_00698_amd.api import Population
+    sides = [3] * 6
+    over = dict(zeta_spring=0.0, zeta_ground=0.0, dt=1e-4, damping=0.999)
+    B = inputs.gaussian_B()
+    G = inputs.random_genomes(6, seed=5)
+    steps, K = 150, 50
+    P = Population(sides, params=table2_params(**over))
+    Gt, Bt = torch.from_numpy(G).to(DEV), torch.from_numpy(B).to(DEV)
+    P.build_from_genomes(Gt, Bt, SR_QUERY_FP32)
+    P.record(K, steps)
+    P.step(steps)
+    dJ = np.random.default_rng(2).uniform(0.5, 1.5, size=6).astype(np.float32)
+    gg = P.backward(torch.from_numpy(dJ).to(DEV), genomes=Gt, B=Bt)["genome"].cpu().numpy().astype(np.float64)
+    checked = 0
+    for r in range(6):
+        lg = orc.query(G[r].astype(np.float64), B.astype(np.float64), 3)
+        srt = np.sort(lg[:, :5], axis=1)
+        if (srt[:, -1] - srt[:, -2]).min() <= 1e-4:
+            continue
+        J, go = orc.genome_fitness_grad(G[r].astype(np.float64), B.astype(np.float64), 3, steps,
+                                        **_oparams(orc, **over))
+        go = go * float(dJ[r])
+        e = float(np.linalg.norm(gg[r] - go) / max(np.linalg.norm(go), 1e-300))
+        say("robot", r, "genome gradient (weighted actuation) relative L2 %.2e" % e)
+        assert e < 2e-2
+        checked += 1
+    assert checked >= 3

@@ -39,14 +39,16 @@ def test_struct_layouts_match_c(tmp_path):
     from paper_2405_00698_amd import _lib
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "softrobot.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(sr_sim_params), sizeof(sr_ga_params),'
-                   ' offsetof(sr_sim_params, flags), offsetof(sr_ga_params, p_mut_thr), offsetof(sr_ga_params, mut_sigma));'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(sr_sim_params), sizeof(sr_ga_params),'
+                   ' offsetof(sr_sim_params, flags), offsetof(sr_ga_params, p_mut_thr), offsetof(sr_ga_params, mut_sigma),'
+                   ' offsetof(sr_sim_params, mu_static), offsetof(sr_sim_params, zeta_ground));'
                    ' return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     out = [int(t) for t in subprocess.check_output([str(exe)]).split()]
     assert out == [C.sizeof(_lib.SimParams), C.sizeof(_lib.GAParams), _lib.SimParams.flags.offset,
-                   _lib.GAParams.p_mut_thr.offset, _lib.GAParams.mut_sigma.offset]
+                   _lib.GAParams.p_mut_thr.offset, _lib.GAParams.mut_sigma.offset,
+                   _lib.SimParams.mu_static.offset, _lib.SimParams.zeta_ground.offset]
 
 
 def test_defaults_and_errors_without_device():
