@@ -12,6 +12,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # no packed FP32 instructions anywhere in the library
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # the step kernels' slot and direction loops must unroll completely
+         # (their per-slot arrays then live in registers, not scratch)
+         "-mllvm", "-pragma-unroll-threshold=1000000",
          "-Wno-unused-command-line-argument"]
 
 

@@ -29,6 +29,24 @@ __host__ __device__ constexpr int dir_len2(int d) {
 // linear offset of direction d on a lattice of side N (index a + N (b + N c))
 __host__ __device__ constexpr int dir_off(int d, int N) { return dir_dx(d) + N * (dir_dy(d) + N * dir_dz(d)); }
 
+// The voxels of a spring: voxel i (0..7) around a lattice point is the one
+// with offset (ox, oy, oz) = (i & 1, i >> 1 & 1, i >> 2) - 1, and the forward
+// spring of direction d from that point lies in vox_cnt(d) of them (4 for an
+// edge, 2 for a face diagonal, 1 for a body diagonal), listed by vox_idx in the
+// mesh build's (z, y, x) order.
+__host__ __device__ constexpr int vox_cnt(int d) {
+    return (dir_dx(d) == 0 ? 2 : 1) * (dir_dy(d) == 0 ? 2 : 1) * (dir_dz(d) == 0 ? 2 : 1);
+}
+__host__ __device__ constexpr int vox_idx(int d, int i) {
+    const int nx = dir_dx(d) == 0 ? 2 : 1, ny = dir_dy(d) == 0 ? 2 : 1;
+    const int ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
+    const int ox = dir_dx(d) == 0 ? ix - 1 : (dir_dx(d) == 1 ? 0 : -1);
+    const int oy = dir_dy(d) == 0 ? iy - 1 : (dir_dy(d) == 1 ? 0 : -1);
+    const int oz = dir_dz(d) == 0 ? iz - 1 : 0;
+    return (ox + 1) + 2 * (oy + 1) + 4 * (oz + 1);
+}
+__host__ __device__ constexpr int vox_off(int i, int N) { return ((i & 1) - 1) + N * (((i >> 1) & 1) - 1) + N * N * ((i >> 2) - 1); }
+
 // Per-robot metadata, device resident.
 struct RobotInfo {
     int32_t n;          // voxels per side
@@ -51,6 +69,10 @@ struct RobotInfo {
 //   kd    dashpot coefficient c beside the spring (Table II model; 0 otherwise).
 struct Planes {
     float *k, *kL0, *kal, *kbe, *kd;
+    // per slot: the parallel-sum terms (k_c w, k_c w a cos, k_c w a sin, dashpot)
+    // of the voxel whose lowest corner is the slot; the planes above are the
+    // explicitly rounded sums of these over each spring's voxels
+    float4 *vkp;
 };
 
 // Node incidence for the per-step kernel: for node i of a robot (slot-space
@@ -121,12 +143,13 @@ hipError_t launch_check_div(const RobotInfo *robots, int R, const float4 *x, con
 
 // persistent LDS-resident kernel for robots of side n; `list` holds the robot
 // ids to step (all of side n).  variant: 0 recompute, 1 exchange, 2 exchange
-// in two direction chunks (+4 fences, +8 12-byte loads, +16 spring dashpots).
+// in two direction chunks (+4 fences, +8 12-byte loads, +16 spring dashpots,
+// +32/+64 parameters rebuilt from voxels, +128 one position buffer).
 struct PersistCfg {
     int n, block, variant;
 };
 bool persist_supported(const PersistCfg &cfg, bool phase);
-int persist_default_block(int n, bool dash, int *variant);
+int persist_default_block(int n, bool dash, bool vox, int *variant);
 int persist_list(int n, int32_t *blocks, int32_t *variants, int cap);
 size_t persist_lds_bytes(const PersistCfg &cfg);
 hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo *robots, const int32_t *list,

@@ -7,6 +7,11 @@
 // timing.
 #include "internal.h"
 
+// No contraction of a*b + c into FMAs in this file: the spring parameters are
+// sums of separately rounded per-voxel products, which the step kernels that
+// rebuild them from voxels repeat operation by operation.
+#pragma clang fp contract(off)
+
 namespace sr {
 
 namespace {
@@ -34,6 +39,25 @@ struct BuildArgs {
     float dash2m;  // 2 m zeta_spring^2: a voxel spring's dashpot is sqrt(dash2m k_c w)
     float voxel_len;
 };
+
+// A kept voxel's contributions to each of its springs (parallel-sum rule):
+// x = k_c w, y = k_c w amp cos(ph), z = k_c w amp sin(ph), w = its dashpot.
+// Separately rounded operations (contraction is off in this file), so that a
+// spring's sums can be rebuilt bit for bit from these per-voxel values.
+__device__ float4 voxel_terms(const BuildArgs &A, int kc, float wv) {
+    const float kw = A.k_class[kc] * wv;
+    float cz, sz;
+    if (A.weight_act) {
+        // amplitude w a_c and phase w phi_c (Table II maxima times the weight)
+        const float amp = wv * A.a_class[kc], ph = wv * A.phi_class[kc];
+        cz = amp * cosf(ph);
+        sz = amp * sinf(ph);
+    } else {
+        cz = A.ac_cos[kc];
+        sz = A.ac_sin[kc];
+    }
+    return make_float4(kw, kw * cz, kw * sz, sqrtf(A.dash2m * kw));
+}
 
 // exclusive prefix sum over the block in thread order; returns the block total in *total
 __device__ int block_exscan(int val, int *tmp, int *total) {
@@ -182,19 +206,11 @@ __global__ __launch_bounds__(BT) void k_build_mesh(BuildArgs A) {
                             if (vx < 0 || vx >= n || vy < 0 || vy >= n || vz < 0 || vz >= n) continue;
                             const int kc = lab[vx + n * (vy + n * vz)];
                             if (!kc) continue;
-                            const float wv = A.w[ri.vox_base + vx + n * (vy + n * vz)];
-                            const float kw = A.k_class[kc] * wv;
-                            ks += kw;
-                            if (A.weight_act) {
-                                // amplitude w a_c and phase w phi_c (Table II maxima times the weight)
-                                const float amp = wv * A.a_class[kc], ph = wv * A.phi_class[kc];
-                                zr += kw * (amp * cosf(ph));
-                                zi += kw * (amp * sinf(ph));
-                            } else {
-                                zr += kw * A.ac_cos[kc];
-                                zi += kw * A.ac_sin[kc];
-                            }
-                            cd += sqrtf(A.dash2m * kw);
+                            const float4 t = voxel_terms(A, kc, A.w[ri.vox_base + vx + n * (vy + n * vz)]);
+                            ks += t.x;
+                            zr += t.y;
+                            zi += t.z;
+                            cd += t.w;
                             ++hits;
                         }
             }
@@ -209,6 +225,14 @@ __global__ __launch_bounds__(BT) void k_build_mesh(BuildArgs A) {
             A.pl.kd[pi] = hits ? cd : 0.f;
         }
         emask[s] = (uint16_t)mask;
+        // the voxel whose lowest corner is this slot, for kernels that rebuild
+        // spring parameters from voxels (zero where there is no kept voxel)
+        float4 vt = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (a < n && b < n && c < n) {
+            const int kc = lab[a + n * (b + n * c)];
+            if (kc) vt = voxel_terms(A, kc, A.w[ri.vox_base + a + n * (b + n * c)]);
+        }
+        A.pl.vkp[ri.slot_base + s] = vt;
     }
     __syncthreads();
 

@@ -70,6 +70,7 @@ struct sr_pop {
     bool built = false;
     bool phase = false;
     bool dash = false;  // spring dashpots: only the +16 persistent kernels
+    bool vox_ok = false;  // the per-voxel terms match the spring planes (no pop_set_spring_params since the build)
     int mode = SR_STEP_AUTO, spl = 0;
     int sticky = 0;
     // genome query scratch
@@ -129,7 +130,7 @@ void pop_free(sr_pop *pop) {
     for (auto s : pop->side) (void)hipStreamDestroy(s);
     for (auto e : pop->ev) (void)hipEventDestroy(e);
     if (pop->cap) (void)hipStreamDestroy(pop->cap);
-    void *ptrs[] = {pop->d_robots, pop->kept, pop->w, pop->pl.k, pop->pl.kL0, pop->pl.kal, pop->pl.kbe, pop->pl.kd,
+    void *ptrs[] = {pop->d_robots, pop->kept, pop->w, pop->pl.k, pop->pl.kL0, pop->pl.kal, pop->pl.kbe, pop->pl.kd, pop->pl.vkp,
                     pop->sid, pop->x0, pop->xbuf[0], pop->xbuf[1], pop->vbuf[0], pop->vbuf[1],
                     pop->slot_node, pop->node_slot, pop->slot_robot, pop->rows, pop->entries,
                     pop->bad_class, pop->diverged, pop->d_step, pop->sc, pop->d_lists, pop->d_mass_off,
@@ -194,6 +195,7 @@ int finish_build(sr_pop *pop) {
             return set_err(SR_EINVAL, "robot %d has a voxel class outside 0..4", r);
         }
     pop->built = true;
+    pop->vox_ok = true;
     return SR_OK;
 }
 
@@ -339,6 +341,7 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
     ALLOC(pop->pl.kal, P);
     ALLOC(pop->pl.kbe, P);
     ALLOC(pop->pl.kd, P);
+    ALLOC(pop->pl.vkp, S);
     ALLOC(pop->sid, P);
     ALLOC(pop->x0, S);
     ALLOC(pop->xbuf[0], S);
@@ -379,7 +382,7 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
         g.offset = (int)lists.size();
         g.count = (int)kv.second.size();
         g.cfg.n = kv.first;
-        g.cfg.block = persist_default_block(kv.first, pop->dash, &g.cfg.variant);
+        g.cfg.block = persist_default_block(kv.first, pop->dash, true, &g.cfg.variant);
         lists.insert(lists.end(), kv.second.begin(), kv.second.end());
         pop->groups.push_back(g);
     }
@@ -478,6 +481,9 @@ int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t varia
             PersistCfg c{n, block, variant};
             if (!persist_supported(c, pop->phase))
                 return set_err(SR_EUNSUPPORTED, "no persistent kernel for n=%d block=%d variant=%d", n, block, variant);
+            if ((variant & 96) && !pop->vox_ok)
+                return set_err(SR_EUNSUPPORTED, "variant %d rebuilds spring parameters from voxels, but they were "
+                               "set with pop_set_spring_params", variant);
             if (((variant & 16) != 0) != pop->dash)
                 return set_err(SR_EUNSUPPORTED, "variant %d %s spring dashpots; this population has %s", variant,
                                (variant & 16) ? "has" : "lacks", pop->dash ? "them" : "none");
@@ -695,6 +701,13 @@ int pop_set_spring_params(sr_pop *pop, const float *k, const float *a, const flo
     if (rc) return rc;
     if (phi) pop->phase = true;
     if (pop->h_step > 0) pop->rec_valid = false;  // the recorded run used other parameters
+    // kernels that rebuild the parameters from voxels would not see the new values
+    pop->vox_ok = false;
+    for (auto &g : pop->groups)
+        if (g.cfg.variant & 96) {
+            g.cfg.block = persist_default_block(g.n, pop->dash, false, &g.cfg.variant);
+            clear_graphs(pop);
+        }
     HIPC(pop, launch_springs_io(pop->d_robots, pop->R, pop->total_slots, pop->slot_robot, pop->slot_node, pop->sid,
                                 pop->d_spring_off, pop->pl, pop->p.voxel_len, nullptr, nullptr, nullptr, nullptr,
                                 nullptr, k, a, phi, 1, pop->st));

@@ -182,15 +182,53 @@ struct PArgs {
     float4 *rec_x, *rec_v;
 };
 
-template <int N, int BS, int VAR, bool DASH = false>
+// Spring parameters rebuilt from voxels (VOX): every spring touching a lattice
+// point lies in one of the 8 voxels sharing that corner, so a slot can rebuild
+// its forward springs' (k, k L0 a cos phi, k L0 a sin phi, dashpot) each step
+// from those 8 voxels' parallel-sum terms, summed in the mesh build's voxel
+// order with the same explicitly rounded operations, i.e. bit for bit the
+// planes.  VOX 1 does so for the 10 face and body diagonals, VOX 2 for all 13
+// directions; the registers this frees hold more slots without spilling.
+// Voxel i of a slot (i = 0..7) is the one with offset (ox, oy, oz) =
+// (i & 1, i >> 1 & 1, i >> 2) - 1 from the slot; the voxels of direction d are
+// those whose unit cell holds both ends, in the build's (z, y, x) order.
+__host__ __device__ constexpr bool from_vox(int VOX, int d) { return VOX >= 2 || (VOX == 1 && dir_len2(d) >= 2); }
+
+// never fused into an FMA, as in the mesh build
+__device__ __forceinline__ float add_nf(float a, float b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ __forceinline__ float mul_nf(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+
+template <int N, int BS, int VAR, bool DASH = false, int VOX = 0, bool SBX = false>
 constexpr size_t lds_bytes() {
     using G = Geo<N>;
     constexpr int NDC = VAR == 0 ? 0 : (NDIR + VAR - 1) / VAR;
-    return (DASH ? 3 : 2) * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL;
+    return ((SBX ? 1 : 2) + (DASH ? 1 : 0)) * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL +
+           (VOX ? sizeof(float4) * G::CL : 0);
 }
 
-template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false>
+template <bool WIDEV>
+struct VoxT {
+    typedef float2 T;
+};
+template <>
+struct VoxT<true> {
+    typedef float4 T;
+};
+__device__ __forceinline__ float4 vox4(float2 v) { return make_float4(v.x, v.y, 0.f, 0.f); }
+__device__ __forceinline__ float4 vox4(float4 v) { return v; }
+__device__ __forceinline__ void vox_store(float2 &d, float4 v) { d = make_float2(v.x, v.y); }
+__device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
+
+template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
+          int VOX = 0, bool SBX = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    static_assert(VOX == 0 || VAR != 0, "voxel-rebuilt parameters need an exchange variant");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
@@ -201,9 +239,11 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     // three distinct LDS objects, so the compiler knows coefficient stores
     // never alias position loads and can keep many loads in flight
     __shared__ float4 xb0[XL];
-    __shared__ float4 xb1[XL];
+    __shared__ float4 xb1[SBX ? 1 : XL];
     __shared__ float coef[NDC > 0 ? NDC * CL : 1];
     __shared__ float4 vb[DASH ? XL : 1];
+    typedef typename VoxT<PHASE || DASH>::T VT;
+    __shared__ VT vv[VOX ? CL : 1];
     __shared__ int bad;
     const int tid = threadIdx.x;
     const SimConst c = A.c;
@@ -220,9 +260,12 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
         const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f);
         for (int i = tid; i < PAD; i += BS) {
             xb0[i] = ghost;
-            xb1[i] = ghost;
             xb0[PAD + SL + i] = ghost;
-            xb1[PAD + SL + i] = ghost;
+            if constexpr (!SBX) {
+                xb1[i] = ghost;
+                xb1[PAD + SL + i] = ghost;
+            }
+            if constexpr (VOX > 0) vox_store(vv[i], make_float4(0.f, 0.f, 0.f, 0.f));
             if constexpr (DASH) {
                 vb[i] = make_float4(0.f, 0.f, 0.f, 0.f);
                 vb[PAD + SL + i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -244,14 +287,16 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
             const float4 V = A.v[base + sc_];
             if (live) {
                 xb0[PAD + s] = X;
-                xb1[PAD + s] = X;
+                if constexpr (!SBX) xb1[PAD + s] = X;
                 if constexpr (DASH) vb[PAD + s] = V;
+                if constexpr (VOX > 0) vox_store(vv[PAD + s], A.pl.vkp[base + s]);
             }
             xr[k] = make_float3(X.x, X.y, X.z);
             vr[k] = make_float3(V.x, V.y, V.z);
             pres[k] = live && X.w != 0.f;
 #pragma unroll
             for (int d = 0; d < NDIR; ++d) {
+                if (from_vox(VOX, d)) continue;
                 const int pi = pbase + d * SL + sc_;
                 pk[k][d] = live ? A.pl.k[pi] : 0.f;
                 pa[k][d] = live ? A.pl.kal[pi] : 0.f;
@@ -277,8 +322,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
         for (int t = 0; t < A.n_steps; ++t) {
             const float2 sct = sc_next;
             if (t + 1 < A.n_steps) sc_next = A.sc[t + 1];
-            const float4 *const xc = (t & 1) ? xb1 : xb0;
-            float4 *const xn = (t & 1) ? xb0 : xb1;
+            const float4 *const xc = (SBX || !(t & 1)) ? xb0 : xb1;
+            float4 *const xn = (SBX || (t & 1)) ? xb0 : xb1;
             float3 Ff[NPT], Fb[NPT];
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
@@ -349,20 +394,50 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
 #pragma unroll
                                 for (int d = d0; d < d1; ++d) VY[DASH ? d : 0] = ldx<WIDE>(vb + s + (PAD + dir_off(d, N)));
                             }
+                            float4 Vx[VOX > 0 ? 8 : 1];
+                            if constexpr (VOX > 0) {
+                                // the voxel terms never change, but they must be re-read every
+                                // step: hoisting them out of the time loop would hold them in
+                                // registers, which is what this variant avoids
+                                int vo = PAD + s;
+                                __asm__ volatile("" : "+v"(vo));
+#pragma unroll
+                                for (int i = 0; i < 8; ++i) Vx[i] = vox4(vv[vo + vox_off(i, N)]);
+                            }
                             float cfv[NDIR];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
                                 const float dx = Y[d].x - xr[k].x, dy = Y[d].y - xr[k].y, dz = Y[d].z - xr[k].z;
+                                float kk, al, be, cd;
+                                if (from_vox(VOX, d)) {
+                                    // the build's sums, term by term in its order
+                                    float4 sm = Vx[VOX > 0 ? vox_idx(d, 0) : 0];
+#pragma unroll
+                                    for (int i = 1; i < vox_cnt(d); ++i) {
+                                        const float4 u = Vx[VOX > 0 ? vox_idx(d, i) : 0];
+                                        sm.x = add_nf(sm.x, u.x);
+                                        sm.y = add_nf(sm.y, u.y);
+                                        if (PHASE) sm.z = add_nf(sm.z, u.z);
+                                        if (DASH) sm.w = add_nf(sm.w, u.w);
+                                    }
+                                    kk = sm.x;
+                                    al = mul_nf(sm.y, L0d(c, d));
+                                    be = PHASE ? mul_nf(sm.z, L0d(c, d)) : 0.f;
+                                    cd = sm.w;
+                                } else {
+                                    kk = pk[k][d];
+                                    al = pa[k][d];
+                                    be = PHASE ? pb[k][d] : 0.f;
+                                    cd = DASH ? pd[k][DASH ? d : 0] : 0.f;
+                                }
                                 float cf;
                                 if constexpr (DASH) {
                                     const float3 W = VY[DASH ? d : 0];
-                                    cf = spring_coef_d<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
-                                                              PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz),
-                                                              pd[k][DASH ? d : 0],
+                                    cf = spring_coef_d<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz),
+                                                              cd,
                                                               rate(W.x - vr[k].x, W.y - vr[k].y, W.z - vr[k].z, dx, dy, dz));
                                 } else {
-                                    cf = spring_coef<PHASE>(pk[k][d], pk[k][d] * L0d(c, d), pa[k][d],
-                                                            PHASE ? pb[k][d] : 0.f, sct.x, sct.y, len2(dx, dy, dz));
+                                    cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz));
                                 }
                                 cfv[d] = cf;
                                 Ff[k].x = fmaf(cf, dx, Ff[k].x);
@@ -401,7 +476,9 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     if (ch + 1 < NCH) __syncthreads();
                 }
             }
-            if constexpr (DASH && VAR == 0) __syncthreads();  // every velocity read of the step is done
+            // every velocity read (dashpots, recompute variant) or position read
+            // (single position buffer) of the step is done before the update
+            if constexpr ((DASH && VAR == 0) || SBX) __syncthreads();
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int s = tid + k * BS;
@@ -553,6 +630,16 @@ struct PersistEntry {
         NN, BS, VAR + 4 * F + 8 * (1 - W), k_persist<NN + 1, BS, VAR, F, false, false, W>,              \
             k_persist<NN + 1, BS, VAR, F, true, false, W>, lds_bytes<NN + 1, BS, VAR>()                 \
     }
+// spring parameters of the face and body diagonals (VOX 1) or of every
+// direction (VOX 2) rebuilt from voxels each step: + 32 VOX; + 128 for one
+// position buffer (one more barrier per step, less LDS)
+#define SR_PV(NN, BS, VAR, VOX, SBX, F)                                                                    \
+    {                                                                                                        \
+        NN, BS, VAR + 4 * F + 32 * VOX + 128 * SBX,                                                          \
+            k_persist<NN + 1, BS, VAR, F, false, false, true, false, VOX, SBX>,                              \
+            k_persist<NN + 1, BS, VAR, F, true, false, true, false, VOX, SBX>,                               \
+            lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()                                                    \
+    }
 // dashpot kernels carry the phase plane always (with a zero plane the results
 // are the same bits as without it)
 #define SR_PD(NN, BS, VAR)                                                                              \
@@ -561,18 +648,27 @@ struct PersistEntry {
             k_persist<NN + 1, BS, VAR, false, true, false, true, true>, lds_bytes<NN + 1, BS, VAR, true>() \
     }
 
-// The first entry of each side is its default configuration.
+// The first entry of each side is its default configuration (the fastest
+// measured: 4096 robots of 10^3; 11^3 and 12^3 robots of an uneven population).
 const PersistEntry kPersist[] = {
+    SR_PE(10, 448, 1, 0, 1),     SR_PV(11, 896, 1, 2, 1, 1),  SR_PV(12, 768, 2, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
     SR_PE(6, 192, 1, 0, 1),   SR_PE(6, 384, 0, 0, 1),   SR_PE(7, 512, 1, 0, 1),   SR_PE(7, 256, 1, 0, 1),  SR_PE(7, 512, 0, 0, 1),
     SR_PE(8, 768, 0, 0, 0), SR_PE(8, 768, 0, 0, 1), SR_PE(8, 768, 1, 0, 0),   SR_PE(8, 768, 1, 0, 1),   SR_PE(8, 384, 1, 0, 1),   SR_PE(8, 256, 1, 0, 1),  SR_PE(8, 384, 1, 1, 1),
     SR_PE(8, 256, 1, 1, 1),   SR_PE(8, 512, 0, 0, 1),   SR_PE(8, 256, 0, 0, 1),   SR_PE(9, 1024, 1, 0, 1), SR_PE(9, 512, 1, 0, 1),
-    SR_PE(9, 512, 1, 1, 1),   SR_PE(9, 1024, 0, 0, 1),  SR_PE(9, 512, 0, 0, 1),   SR_PE(10, 512, 1, 0, 1), SR_PE(10, 448, 1, 0, 1),
+    SR_PE(9, 512, 1, 1, 1),   SR_PE(9, 1024, 0, 0, 1),  SR_PE(9, 512, 0, 0, 1),   SR_PE(10, 512, 1, 0, 1),
     SR_PE(10, 448, 1, 1, 1),  SR_PE(10, 704, 1, 0, 1),  SR_PE(10, 1024, 1, 0, 1), SR_PE(10, 704, 0, 0, 1), SR_PE(10, 704, 2, 0, 1),
     SR_PE(10, 448, 2, 0, 1),  SR_PE(10, 448, 0, 0, 1),  SR_PE(10, 512, 0, 0, 1),  SR_PE(10, 384, 1, 0, 1), SR_PE(11, 896, 1, 0, 1),
     SR_PE(11, 896, 1, 1, 1),  SR_PE(11, 576, 1, 0, 1),  SR_PE(11, 576, 1, 1, 1),  SR_PE(11, 1024, 0, 0, 1), SR_PE(12, 768, 2, 0, 1),
     SR_PE(12, 768, 2, 1, 1),  SR_PE(12, 768, 0, 0, 1),  SR_PE(12, 1024, 2, 0, 1), SR_PE(12, 1024, 2, 1, 1),
+    SR_PE(11, 256, 1, 0, 1),
+    // parameters rebuilt from voxels
+    SR_PV(10, 448, 1, 1, 0, 0),  SR_PV(10, 512, 1, 1, 0, 0),  SR_PV(10, 704, 1, 1, 0, 0),  SR_PV(10, 704, 1, 2, 0, 0),
+    SR_PV(10, 448, 1, 2, 0, 0),  SR_PV(10, 704, 1, 2, 0, 1),  SR_PV(11, 576, 2, 1, 0, 0),  SR_PV(11, 896, 2, 1, 0, 0),
+    SR_PV(11, 896, 2, 2, 0, 0),  SR_PV(11, 896, 2, 2, 0, 1),  SR_PV(11, 576, 2, 2, 0, 1),
+    SR_PV(11, 576, 1, 2, 1, 1),  SR_PV(12, 768, 2, 2, 1, 0),  SR_PV(12, 1024, 2, 2, 1, 1),
+    SR_PV(12, 576, 2, 2, 1, 1),  SR_PV(9, 1024, 1, 1, 0, 0),  SR_PV(8, 768, 1, 1, 0, 0),
     // spring dashpots (Table II model)
     SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
     SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
@@ -596,12 +692,32 @@ const PersistEntry *find_persist(const PersistCfg &cfg) {
     return nullptr;
 }
 
+constexpr int kNumPersist = sizeof(kPersist) / sizeof(kPersist[0]);
+
+// A configuration is usable when both of its kernels (with and without the
+// phase plane) fit in one CU's LDS as compiled: the compiler may place
+// private arrays in LDS too, so the code object, not the formula, decides.
+bool entry_fits(const PersistEntry &e) {
+    static int state[kNumPersist] = {0};  // 0 unknown, 1 fits, 2 does not
+    const int i = (int)(&e - kPersist);
+    if (state[i] == 0) {
+        size_t lds = e.lds;
+        for (PersistFn f : {e.fn, e.fn_phase}) {
+            hipFuncAttributes at;
+            if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(f)) == hipSuccess && at.sharedSizeBytes > lds)
+                lds = at.sharedSizeBytes;
+        }
+        state[i] = lds <= 160 * 1024 ? 1 : 2;
+    }
+    return state[i] == 1;
+}
+
 }  // namespace
 
 bool persist_supported(const PersistCfg &cfg, bool phase) {
     (void)phase;
     const PersistEntry *e = find_persist(cfg);
-    return e && e->lds <= 160 * 1024;
+    return e && entry_fits(*e);
 }
 
 size_t persist_lds_bytes(const PersistCfg &cfg) {
@@ -612,7 +728,7 @@ size_t persist_lds_bytes(const PersistCfg &cfg) {
 int persist_list(int n, int32_t *blocks, int32_t *variants, int cap) {
     int cnt = 0;
     for (const auto &e : kPersist)
-        if (e.n == n && e.lds <= 160 * 1024) {
+        if (e.n == n && entry_fits(e)) {
             if (cnt < cap) {
                 if (blocks) blocks[cnt] = e.block;
                 if (variants) variants[cnt] = e.variant;
@@ -622,9 +738,9 @@ int persist_list(int n, int32_t *blocks, int32_t *variants, int cap) {
     return cnt;
 }
 
-int persist_default_block(int n, bool dash, int *variant) {
+int persist_default_block(int n, bool dash, bool vox, int *variant) {
     for (const auto &e : kPersist)
-        if (e.n == n && e.lds <= 160 * 1024 && ((e.variant & 16) != 0) == dash) {
+        if (e.n == n && ((e.variant & 16) != 0) == dash && (vox || !(e.variant & 96)) && entry_fits(e)) {
             *variant = e.variant;
             return e.block;
         }
@@ -635,7 +751,7 @@ hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo 
                              int grid, Planes pl, float4 *x, float4 *v, const float2 *sc, int n_steps,
                              uint8_t *diverged, SimConst c, hipStream_t st) {
     const PersistEntry *e = find_persist(cfg);
-    if (!e || e->lds > 160 * 1024) return hipErrorInvalidConfiguration;
+    if (!e || !entry_fits(*e)) return hipErrorInvalidConfiguration;
     PArgs A;
     A.robots = robots;
     A.list = list;

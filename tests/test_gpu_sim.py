@@ -106,10 +106,16 @@ def test_plain_and_persistent_agree_bitwise():
     assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
 
 
-@pytest.mark.parametrize("n,configs", [(8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9)]),
+@pytest.mark.parametrize("n,configs", [(8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9),
+                                           (768, 33)]),
+                                       (9, [(1024, 1), (1024, 33), (512, 1)]),
                                        (10, [(512, 1), (448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
-                                             (448, 0), (448, 5), (512, 0), (384, 1)]),
-                                       (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6)])])
+                                             (448, 0), (448, 5), (512, 0), (384, 1), (448, 33), (704, 33), (704, 65),
+                                             (448, 65), (704, 69)]),
+                                       (11, [(896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
+                                             (896, 197), (576, 197)]),
+                                       (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6), (768, 194), (768, 198),
+                                             (1024, 198), (576, 198)])])
 def test_persistent_variants_bitwise(n, configs):
     sides = [n] * 4
     cls, w = voxel_population(sides, 17)
@@ -222,3 +228,25 @@ def test_empty_and_single_voxel_robots(orc):
     P1 = gpu_population([4], *voxel_population([4], 72))
     P1.step(50)
     assert np.isfinite(P1.fitness().cpu().numpy()).all()
+
+
+def test_voxel_rebuilt_parameters_follow_spring_parameter_changes():
+    # kernels that rebuild spring parameters from voxels cannot see parameters
+    # set directly; the population falls back to a stored-parameter kernel
+    from paper_2405_00698_amd import SoftRobotError
+    sides = [10] * 2
+    cls, w = voxel_population(sides, 27)
+    P = gpu_population(sides, cls, w)
+    P.set_persist_variant(10, 448, 33)
+    sp = P.springs()
+    P.set_spring_params(sp["k"] * 1.5, None, None)
+    b, v = P.persist_variant(10)
+    assert not (v & 96)
+    with pytest.raises(SoftRobotError):
+        P.set_persist_variant(10, 448, 33)
+    Q = gpu_population(sides, cls, w)
+    Q.set_spring_params(sp["k"] * 1.5, None, None)
+    Q.set_step_config(SR_STEP_PLAIN)
+    P.step(100)
+    Q.step(100)
+    assert torch.equal(P.state()[0], Q.state()[0])

@@ -71,3 +71,32 @@ def test_product_path_does_not_touch_the_oracle():
         if f.endswith((".py", ".hip", ".h", ".cpp")):
             txt = open(f).read()
             assert "import oracle" not in txt and "from oracle" not in txt and "oracle.c" not in txt, f
+
+
+def test_voxel_order_of_rebuilt_parameters_matches_mesh_ranges(tmp_path):
+    """The kernels that rebuild spring parameters from voxels must add a
+    spring's voxels in the mesh build's order.  The build takes, per axis, the
+    voxel range [min(a, a2) - (step == 0), min(a, a2)] (z: [c - 1 + dz, c]) and
+    loops z, y, x ascending; the helpers in internal.h are compiled on the host
+    and compared with that enumeration for all 13 directions."""
+    src = tmp_path / "vox.cpp"
+    src.write_text('#include <cstdio>\n#include "internal.h"\nusing namespace sr;\n'
+                   'int main(){for(int d=0;d<NDIR;++d){printf("%d %d %d %d",dir_dx(d),dir_dy(d),dir_dz(d),vox_cnt(d));'
+                   'for(int i=0;i<vox_cnt(d);++i)printf(" %d",vox_idx(d,i));printf("\\n");}'
+                   'for(int i=0;i<8;++i)printf("%d ",vox_off(i,11));printf("\\n");return 0;}\n')
+    exe = tmp_path / "vox"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "-x", "hip", "--offload-arch=gfx950", "-std=c++17", "-I",
+                           os.path.join(ROOT, "paper_2405_00698_amd", "csrc"), str(src), "-o", str(exe)])
+    lines = subprocess.check_output([str(exe)]).decode().split("\n")
+    for line in lines[:13]:
+        dx, dy, dz, cnt, *idx = [int(t) for t in line.split()]
+        a = b = c = 5
+        a2, b2 = a + dx, b + dy
+        want = [(vx - a, vy - b, vz - c)
+                for vz in range(c - 1 + dz, c + 1)
+                for vy in range(min(b, b2) - (dy == 0), min(b, b2) + 1)
+                for vx in range(min(a, a2) - (dx == 0), min(a, a2) + 1)]
+        got = [((i & 1) - 1, ((i >> 1) & 1) - 1, (i >> 2) - 1) for i in idx]
+        assert cnt == len(want) and got == want, (dx, dy, dz, got, want)
+    offs = [int(t) for t in lines[13].split()]
+    assert offs == [((i & 1) - 1) + 11 * (((i >> 1) & 1) - 1) + 121 * ((i >> 2) - 1) for i in range(8)]
