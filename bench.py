@@ -198,7 +198,7 @@ def main():
         # pick the fastest compiled step-kernel configuration for this population (cached)
         from paper_2405_00698_amd import tune
         P.build_from_genomes(Gt[0], Bt, prec)
-        tuned = {int(k): list(v) for k, v in tune.tune(P, steps=200, cache_path="/tmp/softrobot_tune.json").items()}
+        tuned = {int(k): list(v) for k, v in tune.tune(P, steps=500, cache_path="/tmp/softrobot_tune.json").items()}
 
     stream = torch.cuda.current_stream()
     springs_per_gen = []

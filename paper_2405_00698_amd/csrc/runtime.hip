@@ -82,10 +82,16 @@ struct sr_pop {
     bool rec_valid = false;
     float4 *ck_x = nullptr, *ck_v = nullptr;
     // adjoint scratch (grown on demand)
+    // (two sets of segment buffers: segment s - 1 is recomputed on adj_st while
+    // segment s is reversed on the population's stream)
     int rec_cap = 0;
-    float4 *rec_x = nullptr, *rec_v = nullptr, *tmp_x = nullptr, *tmp_v = nullptr, *lx = nullptr, *lv = nullptr;
+    float4 *rec_x[2] = {nullptr, nullptr}, *rec_v[2] = {nullptr, nullptr};
+    float4 *tmp_x[2] = {nullptr, nullptr}, *tmp_v[2] = {nullptr, nullptr};
+    float4 *lx = nullptr, *lv = nullptr;
     float *gk = nullptr, *gs = nullptr, *gc = nullptr, *dJdw = nullptr;
-    float2 *sc_seg = nullptr;
+    float2 *sc_seg[2] = {nullptr, nullptr};
+    hipStream_t adj_st = nullptr;
+    hipEvent_t adj_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // start, recorded[2], reversed[2]
     // captured step graphs: one per (n_steps, mode, current buffer, steps per launch)
     bool use_graphs = true;
     hipStream_t cap = nullptr;
@@ -135,10 +141,14 @@ void pop_free(sr_pop *pop) {
                     pop->slot_node, pop->node_slot, pop->slot_robot, pop->rows, pop->entries,
                     pop->bad_class, pop->diverged, pop->d_step, pop->sc, pop->d_lists, pop->d_mass_off,
                     pop->d_spring_off, pop->q_cls, pop->q_w, pop->vox_robot, pop->ck_x, pop->ck_v,
-                    pop->rec_x, pop->rec_v, pop->tmp_x, pop->tmp_v, pop->lx, pop->lv, pop->gk, pop->gs,
-                    pop->gc, pop->dJdw, pop->sc_seg};
+                    pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
+                    pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs,
+                    pop->gc, pop->dJdw, pop->sc_seg[0], pop->sc_seg[1]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (auto e : pop->adj_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (pop->adj_st) (void)hipStreamDestroy(pop->adj_st);
 }
 
 int ensure_counts(sr_pop *pop) {
@@ -797,22 +807,29 @@ namespace {
 int ensure_adj_scratch(sr_pop *pop, int K) {
     if (K <= pop->rec_cap) return SR_OK;
     HIPC(pop, hipStreamSynchronize(pop->st));
-    void *old[] = {pop->rec_x, pop->rec_v, pop->tmp_x, pop->tmp_v, pop->lx, pop->lv, pop->gk, pop->gs, pop->gc,
-                   pop->dJdw, pop->sc_seg};
+    void *old[] = {pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
+                   pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs, pop->gc,
+                   pop->dJdw, pop->sc_seg[0], pop->sc_seg[1]};
     for (void *p : old)
         if (p) HIPC(pop, hipFree(p));
     const size_t S = pop->total_slots;
-    hipError_t e = dalloc(&pop->rec_x, S * K);
-    if (e == hipSuccess) e = dalloc(&pop->rec_v, S * K);
-    if (e == hipSuccess) e = dalloc(&pop->tmp_x, S);
-    if (e == hipSuccess) e = dalloc(&pop->tmp_v, S);
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < 2; ++b) {
+        if (e == hipSuccess) e = dalloc(&pop->rec_x[b], S * K);
+        if (e == hipSuccess) e = dalloc(&pop->rec_v[b], S * K);
+        if (e == hipSuccess) e = dalloc(&pop->tmp_x[b], S);
+        if (e == hipSuccess) e = dalloc(&pop->tmp_v[b], S);
+        if (e == hipSuccess) e = dalloc(&pop->sc_seg[b], (size_t)K);
+    }
     if (e == hipSuccess) e = dalloc(&pop->lx, S);
     if (e == hipSuccess) e = dalloc(&pop->lv, S);
     if (e == hipSuccess) e = dalloc(&pop->gk, S * NDIR);
     if (e == hipSuccess) e = dalloc(&pop->gs, S * NDIR);
     if (e == hipSuccess) e = dalloc(&pop->gc, S * NDIR);
     if (e == hipSuccess) e = dalloc(&pop->dJdw, (size_t)pop->total_vox);
-    if (e == hipSuccess) e = dalloc(&pop->sc_seg, (size_t)K);
+    if (e == hipSuccess && !pop->adj_st) e = hipStreamCreateWithFlags(&pop->adj_st, hipStreamNonBlocking);
+    for (auto &ev : pop->adj_ev)
+        if (e == hipSuccess && !ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         pop->rec_cap = 0;
         return set_err(SR_ENOMEM, "adjoint scratch: %s", hipGetErrorString(e));
@@ -844,23 +861,44 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
                               pop->gk, pop->gs, pop->gc, pop->st));
     const int64_t T = pop->h_step;
     const int nseg = (int)((T + K - 1) / K);
-    for (int seg = nseg - 1; seg >= 0; --seg) {
+    // Segments are reversed last to first on the population's stream.  The
+    // recomputation (checkpoint -> recorded states) of the segment before runs
+    // meanwhile on adj_st into the other buffer set, so a population too small
+    // to fill the GPU overlaps the two; events order every buffer reuse.
+    hipEvent_t ev_start = pop->adj_ev[0], *ev_rec = pop->adj_ev + 1, *ev_rev = pop->adj_ev + 3;
+    HIPC(pop, hipEventRecord(ev_start, pop->st));
+    HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_start, 0));
+    auto recompute = [&](int seg) -> int {
+        const int b = seg & 1;
         const int64_t s0 = (int64_t)seg * K;
         const int len = (int)((T - s0) < K ? (T - s0) : K);
         const size_t off = (size_t)seg * pop->total_slots;
-        HIPC(pop, hipMemcpyAsync(pop->tmp_x, pop->ck_x + off, sizeof(float4) * pop->total_slots,
-                                 hipMemcpyDeviceToDevice, pop->st));
-        HIPC(pop, hipMemcpyAsync(pop->tmp_v, pop->ck_v + off, sizeof(float4) * pop->total_slots,
-                                 hipMemcpyDeviceToDevice, pop->st));
-        HIPC(pop, launch_sincos_at(pop->sc_seg, s0, len, omega_dt, pop->c.actuation, pop->st));
+        // buffer set b was last read by the reversal of segment seg + 2
+        if (seg + 2 < nseg) HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_rev[b], 0));
+        HIPC(pop, hipMemcpyAsync(pop->tmp_x[b], pop->ck_x + off, sizeof(float4) * pop->total_slots,
+                                 hipMemcpyDeviceToDevice, pop->adj_st));
+        HIPC(pop, hipMemcpyAsync(pop->tmp_v[b], pop->ck_v + off, sizeof(float4) * pop->total_slots,
+                                 hipMemcpyDeviceToDevice, pop->adj_st));
+        HIPC(pop, launch_sincos_at(pop->sc_seg[b], s0, len, omega_dt, pop->c.actuation, pop->adj_st));
         for (const auto &gr : pop->groups)
             HIPC(pop, launch_record(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count, pop->pl,
-                                    pop->tmp_x, pop->tmp_v, pop->sc_seg, len, pop->diverged, pop->c, pop->rec_x,
-                                    pop->rec_v, pop->st));
+                                    pop->tmp_x[b], pop->tmp_v[b], pop->sc_seg[b], len, pop->diverged, pop->c,
+                                    pop->rec_x[b], pop->rec_v[b], pop->adj_st));
+        HIPC(pop, hipEventRecord(ev_rec[b], pop->adj_st));
+        return SR_OK;
+    };
+    if (nseg > 0 && (rc = recompute(nseg - 1))) return rc;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int b = seg & 1;
+        const int64_t s0 = (int64_t)seg * K;
+        const int len = (int)((T - s0) < K ? (T - s0) : K);
+        if (seg > 0 && (rc = recompute(seg - 1))) return rc;
+        HIPC(pop, hipStreamWaitEvent(pop->st, ev_rec[b], 0));
         for (const auto &gr : pop->groups)
             HIPC(pop, launch_adjoint(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count, pop->pl,
-                                     pop->x0, pop->rec_x, pop->rec_v, len, pop->sc_seg, pop->lx, pop->lv, pop->gk,
-                                     pop->gs, pop->gc, pop->c, pop->st));
+                                     pop->x0, pop->rec_x[b], pop->rec_v[b], len, pop->sc_seg[b], pop->lx, pop->lv,
+                                     pop->gk, pop->gs, pop->gc, pop->c, pop->st));
+        HIPC(pop, hipEventRecord(ev_rev[b], pop->st));
     }
     HIPC(pop, launch_adj_springs(pop->d_robots, pop->total_slots, pop->slot_robot, pop->sid, pop->d_spring_off, pop->pl,
                                  pop->p.voxel_len, pop->gk, pop->gs, pop->gc, g_k, g_a, g_phi, pop->st));
