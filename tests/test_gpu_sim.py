@@ -250,3 +250,27 @@ def test_voxel_rebuilt_parameters_follow_spring_parameter_changes():
     P.step(100)
     Q.step(100)
     assert torch.equal(P.state()[0], Q.state()[0])
+
+
+def test_uneven_population_sampled_parity(orc):
+    """The uneven workload at size (1024 robots, sides 4..12, empty fractions
+    0.1..0.5, BF16-MFMA build) in the benchmark's launch configuration: one
+    robot of every side, rebuilt by the oracle from the GPU's per-voxel
+    build input, is compared after 200 steps with contact."""
+    from paper_2405_00698_amd import SR_QUERY_BF16, inputs
+    from paper_2405_00698_amd.api import Population
+    R = 1024
+    sides = [int(q) for q in inputs.grid_sides(R, 4, 12)]
+    G = inputs.random_genomes(R, seed=1, empty_bias=inputs.uniform(R, -0.2, 0.4, seed=2))
+    P = Population(sides)
+    P.build_from_genomes(torch.from_numpy(G).to(DEV), torch.from_numpy(inputs.gaussian_B()).to(DEV), SR_QUERY_BF16)
+    cls, w = (t.cpu().numpy() for t in P.query())
+    P.step(200)
+    xs, _, _ = gpu_states(P)
+    offs = np.concatenate([[0], np.cumsum([n ** 3 for n in sides])])
+    for n in range(4, 13):
+        r = sides.index(n)
+        say("uneven sample robot", r, "side", n, P.kernel_config(n))
+        Rb = orc.Robot(n, cls[offs[r]:offs[r + 1]], w[offs[r]:offs[r + 1]].astype(np.float64))
+        Rb.step(200)
+        assert rel_err(xs[r], Rb.state()[0]) <= 1e-3, (r, n)
