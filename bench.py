@@ -256,7 +256,7 @@ def main():
                                 "%d robots with sides uniform on 4..12" % R) +
                                ", %d sim steps per generation (dt 1e-4 s), %s genome query, GA %s"
                                % (args.sim_steps, args.query, "on" if has_ga else "off"),
-                   "robots": R, "grid_side": n, "sim_steps": args.sim_steps, "mode": args.mode,
+                   "robots": R, "grid_side": n if args.workload == "uniform" else "4..12", "sim_steps": args.sim_steps, "mode": args.mode,
                    "springs_per_generation": springs_per_gen[0][0], "masses_per_generation": springs_per_gen[0][1],
                    "step_kernel": {q: P.kernel_config(q) for q in sorted(set(sides))}, "tuned": tuned},
         "sim_kernel_s": kern_s,

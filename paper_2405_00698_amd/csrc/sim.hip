@@ -648,10 +648,13 @@ struct PersistEntry {
             k_persist<NN + 1, BS, VAR, false, true, false, true, true>, lds_bytes<NN + 1, BS, VAR, true>() \
     }
 
-// The first entry of each side is its default configuration (the fastest
-// measured: 4096 robots of 10^3; 11^3 and 12^3 robots of an uneven population).
+// The first entry of each side is its default configuration, the first one
+// without voxel terms the default when the spring parameters were set directly
+// (the fastest measured: 4096 robots of 10^3; 11^3 and 12^3 robots of an uneven
+// population).
 const PersistEntry kPersist[] = {
-    SR_PE(10, 448, 1, 0, 1),     SR_PV(11, 896, 1, 2, 1, 1),  SR_PV(12, 768, 2, 2, 1, 1),
+    SR_PE(10, 448, 1, 0, 1),     SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(12, 768, 2, 2, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
+    SR_PE(11, 256, 1, 0, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
     SR_PE(6, 192, 1, 0, 1),   SR_PE(6, 384, 0, 0, 1),   SR_PE(7, 512, 1, 0, 1),   SR_PE(7, 256, 1, 0, 1),  SR_PE(7, 512, 0, 0, 1),
@@ -662,13 +665,15 @@ const PersistEntry kPersist[] = {
     SR_PE(10, 448, 2, 0, 1),  SR_PE(10, 448, 0, 0, 1),  SR_PE(10, 512, 0, 0, 1),  SR_PE(10, 384, 1, 0, 1), SR_PE(11, 896, 1, 0, 1),
     SR_PE(11, 896, 1, 1, 1),  SR_PE(11, 576, 1, 0, 1),  SR_PE(11, 576, 1, 1, 1),  SR_PE(11, 1024, 0, 0, 1), SR_PE(12, 768, 2, 0, 1),
     SR_PE(12, 768, 2, 1, 1),  SR_PE(12, 768, 0, 0, 1),  SR_PE(12, 1024, 2, 0, 1), SR_PE(12, 1024, 2, 1, 1),
-    SR_PE(11, 256, 1, 0, 1),
+    SR_PE(10, 256, 1, 0, 1),  SR_PE(9, 256, 1, 0, 1),   SR_PE(12, 256, 2, 0, 1),
     // parameters rebuilt from voxels
     SR_PV(10, 448, 1, 1, 0, 0),  SR_PV(10, 512, 1, 1, 0, 0),  SR_PV(10, 704, 1, 1, 0, 0),  SR_PV(10, 704, 1, 2, 0, 0),
     SR_PV(10, 448, 1, 2, 0, 0),  SR_PV(10, 704, 1, 2, 0, 1),  SR_PV(11, 576, 2, 1, 0, 0),  SR_PV(11, 896, 2, 1, 0, 0),
     SR_PV(11, 896, 2, 2, 0, 0),  SR_PV(11, 896, 2, 2, 0, 1),  SR_PV(11, 576, 2, 2, 0, 1),
     SR_PV(11, 576, 1, 2, 1, 1),  SR_PV(12, 768, 2, 2, 1, 0),  SR_PV(12, 1024, 2, 2, 1, 1),
     SR_PV(12, 576, 2, 2, 1, 1),  SR_PV(9, 1024, 1, 1, 0, 0),  SR_PV(8, 768, 1, 1, 0, 0),
+    // one wave per SIMD, many slots per thread
+    SR_PV(10, 256, 1, 2, 0, 1),  SR_PV(10, 256, 1, 1, 0, 1),  SR_PV(11, 256, 1, 2, 1, 1),  SR_PV(12, 256, 2, 2, 1, 1),
     // spring dashpots (Table II model)
     SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
     SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
