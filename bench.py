@@ -31,10 +31,12 @@ VALU_SLOTS_PER_SPRING = 18.0                 # one force evaluation applied to b
 VALU_SLOTS_PER_MASS = 20.0                   # gravity, ground, friction, damping, integrate
 
 
-def measured_traffic(kernel_cfg, sim_steps):
+def measured_traffic(kernel_cfg, sim_steps, key="hbm_bytes_per_launch"):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE passes (scaled by a copy probe), or None when the
-    kernel source or the launch differs from the one measured."""
+    FETCH_SIZE / WRITE_SIZE passes (scaled by a copy probe), or with
+    key="lds_bytes_per_launch" the LDS bytes its instructions moved (LDS
+    bandwidth counters); None when the kernel source or the launch differs from
+    the one measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
@@ -45,7 +47,7 @@ def measured_traffic(kernel_cfg, sim_steps):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != d["source_sha256"] or d["launch_steps"] != sim_steps or d["kernel"] != kernel_cfg:
         return None
-    return d["hbm_bytes_per_launch"]
+    return d.get(key)
 
 
 def parse():
@@ -239,6 +241,10 @@ def main():
     lds_bytes = su_per_launch * LDS_B_PER_SPRING + mu_per_launch * LDS_B_PER_MASS
     lds_gbs = lds_bytes / kern_s / 1e9
     valu = (su_per_launch * VALU_SLOTS_PER_SPRING + mu_per_launch * VALU_SLOTS_PER_MASS) / kern_s
+    # LDS bytes the kernel's instructions actually moved per launch (counters),
+    # against the algorithmic bytes above
+    lds_traffic = (measured_traffic(P.kernel_config(n), args.sim_steps, "lds_bytes_per_launch")
+                   if args.mode == "persistent" and args.workload == "uniform" else None)
     out = {
         "metric": "spring updates/sec at 1 GPU (% LDS roofline); adjoint/forward time ratio",
         "value": value,
@@ -269,7 +275,8 @@ def main():
                      "traffic": measured_traffic(P.kernel_config(n), args.sim_steps)
                      if args.mode == "persistent" and args.workload == "uniform" else None},
         "roofline_lds": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                         "frac": lds_gbs / LDS_PEAK_GBS},
+                         "frac": lds_gbs / LDS_PEAK_GBS, "traffic": lds_traffic,
+                         "traffic_frac": None if lds_traffic is None else lds_traffic / kern_s / 1e9 / LDS_PEAK_GBS},
         "floors_s": {"alu": (su_per_launch * VALU_SLOTS_PER_SPRING + mu_per_launch * VALU_SLOTS_PER_MASS)
                      / VALU_PEAK_SLOTS, "lds": lds_bytes / (LDS_PEAK_GBS * 1e9)},
     }
