@@ -39,8 +39,12 @@ struct AArgs {
 // entries in front); otherwise the upper end recomputes it.  Both give the
 // same bits.  The exchange keeps one position/adjoint buffer and adds a
 // barrier per step.
-template <int N, int BS, bool PHASE, bool XCH>
+// ALAG (exchange form): the position and adjoint reads of direction d + ALAG
+// are issued before direction d's arithmetic, which waits for its own two reads
+// only (ALAG 0: each read is waited for before the next is issued).
+template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0>
 __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
+    static_assert(ALAG == 0 || XCH, "pipelined reads are for the exchange form");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
@@ -170,11 +174,33 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 const float4 *xsb = xs[b] + s;
                 const float4 *lfb = lf[b] + s;
                 float3 acc = make_float3(0.f, 0.f, 0.f);
+                float4 QY[NDIR], QL[NDIR];
+                if constexpr (ALAG > 0) {
+#pragma unroll
+                    for (int d = 0; d < ALAG && d < NDIR; ++d) {
+                        QY[d] = xsb[PAD + dir_off(d, N)];
+                        QL[d] = lfb[PAD + dir_off(d, N)];
+                    }
+                }
 #pragma unroll
                 for (int d = 0; d < NDIR; ++d) {
                     // forward spring: self is the lower end
-                    const float3 Y = ld3(xsb + (PAD + dir_off(d, N)));
-                    const float3 LJ = ld3(lfb + (PAD + dir_off(d, N)));
+                    float3 Y, LJ;
+                    if constexpr (ALAG > 0) {
+                        constexpr int dummy = 0;
+                        const int e = d + ALAG < NDIR ? d + ALAG : dummy;
+                        if (d + ALAG < NDIR) {
+                            QY[e] = xsb[PAD + dir_off(e, N)];
+                            QL[e] = lfb[PAD + dir_off(e, N)];
+                        }
+                        keep_w(QY[d].w);
+                        keep_w(QL[d].w);
+                        Y = make_float3(QY[d].x, QY[d].y, QY[d].z);
+                        LJ = make_float3(QL[d].x, QL[d].y, QL[d].z);
+                    } else {
+                        Y = ld3(xsb + (PAD + dir_off(d, N)));
+                        LJ = ld3(lfb + (PAD + dir_off(d, N)));
+                    }
                     const float dx = Y.x - Xr[k].x, dy = Y.y - Xr[k].y, dz = Y.z - Xr[k].z;
                     const float ux = LJ.x - LF[k].x, uy = LJ.y - LF[k].y, uz = LJ.z - LF[k].z;
                     const float r2 = len2(dx, dy, dz);
@@ -544,8 +570,10 @@ struct AdjEntry {
 };
 #define SR_AE(NN, BS, X) \
     { NN, BS, k_adjoint<NN + 1, BS, false, X>, k_adjoint<NN + 1, BS, true, X> }
-const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AE(4, 128, true),
-                         SR_AE(5, 256, true),   SR_AE(6, 384, true),   SR_AE(7, 512, true),  SR_AE(8, 768, true),
+#define SR_AEL(NN, BS, LG) \
+    { NN, BS, k_adjoint<NN + 1, BS, false, true, LG>, k_adjoint<NN + 1, BS, true, true, LG> }
+const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
+                         SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AEL(8, 768, 2),
                          SR_AE(9, 1024, false), SR_AE(10, 704, false), SR_AE(11, 1024, false)};
 
 }  // namespace

@@ -225,10 +225,16 @@ __device__ __forceinline__ float4 vox4(float4 v) { return v; }
 __device__ __forceinline__ void vox_store(float2 &d, float4 v) { d = make_float2(v.x, v.y); }
 __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 
+// LAG (exchange variants, 16-byte reads): the neighbour reads of a slot are
+// issued back to back with at most LAG + 1 outstanding; the read LAG places
+// earlier is waited for by keeping its .w alive, the last LAG ones where their
+// direction's arithmetic needs them anyway.  LAG 0 waits for each read before
+// issuing the next.
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
-          int VOX = 0, bool SBX = false>
+          int VOX = 0, bool SBX = false, int LAG = 0>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     static_assert(VOX == 0 || VAR != 0, "voxel-rebuilt parameters need an exchange variant");
+    static_assert(LAG == 0 || VAR == 1, "pipelined reads need the one-chunk exchange (constant direction indices)");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
@@ -388,8 +394,19 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
                             float3 Y[NDIR], VY[DASH ? NDIR : 1];
+                            float Wk[NDIR];
+                            if constexpr (WIDE && LAG > 0) {
 #pragma unroll
-                            for (int d = d0; d < d1; ++d) Y[d] = ldx<WIDE>(xs + (PAD + dir_off(d, N)));
+                                for (int d = d0; d < d1; ++d) {
+                                    const float4 q = xs[PAD + dir_off(d, N)];
+                                    Y[d] = make_float3(q.x, q.y, q.z);
+                                    Wk[d] = q.w;
+                                    if (d - LAG >= d0) keep_w(Wk[d - LAG >= 0 ? d - LAG : 0]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int d = d0; d < d1; ++d) Y[d] = ldx<WIDE>(xs + (PAD + dir_off(d, N)));
+                            }
                             if constexpr (DASH) {
 #pragma unroll
                                 for (int d = d0; d < d1; ++d) VY[DASH ? d : 0] = ldx<WIDE>(vb + s + (PAD + dir_off(d, N)));
@@ -407,6 +424,9 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             float cfv[NDIR];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
+                                if constexpr (WIDE && LAG > 0) {
+                                    if (d + LAG >= d1) keep_w(Wk[d]);
+                                }
                                 const float dx = Y[d].x - xr[k].x, dy = Y[d].y - xr[k].y, dz = Y[d].z - xr[k].z;
                                 float kk, al, be, cd;
                                 if (from_vox(VOX, d)) {
@@ -457,14 +477,24 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             const float4 *xs = xc + s;
                             const float *cs = coef + s;
                             float3 Y[NDIR];
-                            float cfv[NDIR];
+                            float cfv[NDIR], Wk[NDIR];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
-                                Y[d] = ldx<WIDE>(xs + (PAD - dir_off(d, N)));
+                                if constexpr (WIDE && LAG > 0) {
+                                    const float4 q = xs[PAD - dir_off(d, N)];
+                                    Y[d] = make_float3(q.x, q.y, q.z);
+                                    Wk[d] = q.w;
+                                    if (d - LAG >= d0) keep_w(Wk[d - LAG >= 0 ? d - LAG : 0]);
+                                } else {
+                                    Y[d] = ldx<WIDE>(xs + (PAD - dir_off(d, N)));
+                                }
                                 cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
                             }
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
+                                if constexpr (WIDE && LAG > 0) {
+                                    if (d + LAG >= d1) keep_w(Wk[d]);
+                                }
                                 const float ex = Y[d].x - xr[k].x, ey = Y[d].y - xr[k].y, ez = Y[d].z - xr[k].z;
                                 Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
                                 Fb[k].y = fmaf(cfv[d], ey, Fb[k].y);
@@ -640,6 +670,20 @@ struct PersistEntry {
             k_persist<NN + 1, BS, VAR, F, true, false, true, false, VOX, SBX>,                               \
             lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()                                                    \
     }
+// pipelined 16-byte neighbour reads: + 256 * LAG
+#define SR_PL(NN, BS, VAR, F, LG)                                                                          \
+    {                                                                                                        \
+        NN, BS, VAR + 4 * F + 256 * LG,                                                                      \
+            k_persist<NN + 1, BS, VAR, F, false, false, true, false, 0, false, LG>,                          \
+            k_persist<NN + 1, BS, VAR, F, true, false, true, false, 0, false, LG>, lds_bytes<NN + 1, BS, VAR>() \
+    }
+#define SR_PVL(NN, BS, VAR, VOX, SBX, F, LG)                                                              \
+    {                                                                                                        \
+        NN, BS, VAR + 4 * F + 32 * VOX + 128 * SBX + 256 * LG,                                               \
+            k_persist<NN + 1, BS, VAR, F, false, false, true, false, VOX, SBX, LG>,                          \
+            k_persist<NN + 1, BS, VAR, F, true, false, true, false, VOX, SBX, LG>,                           \
+            lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()                                                    \
+    }
 // dashpot kernels carry the phase plane always (with a zero plane the results
 // are the same bits as without it)
 #define SR_PD(NN, BS, VAR)                                                                              \
@@ -653,8 +697,9 @@ struct PersistEntry {
 // (the fastest measured: 4096 robots of 10^3; 11^3 and 12^3 robots of an uneven
 // population).
 const PersistEntry kPersist[] = {
-    SR_PE(10, 448, 1, 0, 1),     SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(12, 768, 2, 2, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
-    SR_PE(11, 256, 1, 0, 1),
+    SR_PL(4, 128, 1, 0, 4),   SR_PL(5, 256, 1, 0, 4),   SR_PL(6, 384, 1, 0, 4),   SR_PL(7, 512, 1, 0, 4),
+    SR_PL(8, 768, 1, 0, 4),   SR_PL(9, 1024, 1, 0, 8),  SR_PE(10, 448, 1, 0, 1),  SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
     SR_PE(6, 192, 1, 0, 1),   SR_PE(6, 384, 0, 0, 1),   SR_PE(7, 512, 1, 0, 1),   SR_PE(7, 256, 1, 0, 1),  SR_PE(7, 512, 0, 0, 1),
@@ -674,6 +719,11 @@ const PersistEntry kPersist[] = {
     SR_PV(12, 576, 2, 2, 1, 1),  SR_PV(9, 1024, 1, 1, 0, 0),  SR_PV(8, 768, 1, 1, 0, 0),
     // one wave per SIMD, many slots per thread
     SR_PV(10, 256, 1, 2, 0, 1),  SR_PV(10, 256, 1, 1, 0, 1),  SR_PV(11, 256, 1, 2, 1, 1),  SR_PV(12, 256, 2, 2, 1, 1),
+    // pipelined neighbour reads
+    SR_PL(10, 448, 1, 0, 2),  SR_PL(10, 448, 1, 0, 4),  SR_PL(10, 448, 1, 0, 6),  SR_PL(10, 512, 1, 0, 4),
+    SR_PL(9, 1024, 1, 0, 4),  SR_PL(11, 256, 1, 0, 4),  SR_PL(8, 768, 1, 0, 8),   SR_PL(8, 768, 1, 0, 12),
+    SR_PL(9, 512, 1, 0, 4),   SR_PL(8, 256, 1, 0, 4),   SR_PVL(10, 448, 1, 1, 0, 0, 4),  SR_PVL(10, 512, 1, 1, 0, 0, 4),
+    SR_PVL(10, 512, 1, 2, 0, 0, 4),  SR_PVL(11, 256, 1, 1, 1, 1, 4),
     // spring dashpots (Table II model)
     SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
     SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
@@ -684,11 +734,17 @@ const PersistEntry kPersist[] = {
 
 #define SR_REC(NN, BS, VAR) \
     { NN, BS, VAR, k_persist<NN + 1, BS, VAR, false, false, true>, k_persist<NN + 1, BS, VAR, false, true, true>, 0 }
+#define SR_RECL(NN, BS, LG)                                                                      \
+    {                                                                                            \
+        NN, BS, 1 + 256 * LG, k_persist<NN + 1, BS, 1, false, false, true, true, false, 0, false, LG>, \
+            k_persist<NN + 1, BS, 1, false, true, true, true, false, 0, false, LG>, 0            \
+    }
 
 // recording forms (used to recompute checkpointed segments for the adjoint)
 const PersistEntry kRec[] = {
-    SR_REC(1, 64, 1),   SR_REC(2, 64, 1),  SR_REC(3, 64, 1),  SR_REC(4, 128, 1),  SR_REC(5, 256, 1),  SR_REC(6, 384, 1),
-    SR_REC(7, 512, 1),  SR_REC(8, 768, 0), SR_REC(9, 1024, 1), SR_REC(10, 448, 1), SR_REC(11, 896, 1), SR_REC(12, 768, 2),
+    SR_REC(1, 64, 1),     SR_REC(2, 64, 1),     SR_REC(3, 64, 1),     SR_RECL(4, 128, 4),  SR_RECL(5, 256, 4),
+    SR_RECL(6, 384, 4),   SR_RECL(7, 512, 4),   SR_RECL(8, 768, 4),   SR_RECL(9, 1024, 8), SR_REC(10, 448, 1),
+    SR_REC(11, 896, 1),   SR_REC(12, 768, 2),
 };
 
 const PersistEntry *find_persist(const PersistCfg &cfg) {

@@ -65,6 +65,10 @@ __device__ __forceinline__ float3 ld3(const float4 *p) {
     return make_float3(v.x, v.y, v.z);
 }
 
+// Keeps a loaded .w alive without using it: the empty asm makes the compiler
+// wait for that one load (and keeps the load 16 bytes wide), nothing else.
+__device__ __forceinline__ void keep_w(float w) { __asm__("" ::"v"(w)); }
+
 // xyz of a float4 slot as one 12-byte read (fewer registers in flight).
 typedef float f3v __attribute__((ext_vector_type(3)));
 __device__ __forceinline__ float3 ld3n(const float4 *p) {

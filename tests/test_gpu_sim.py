@@ -106,14 +106,17 @@ def test_plain_and_persistent_agree_bitwise():
     assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
 
 
-@pytest.mark.parametrize("n,configs", [(8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9),
-                                           (768, 33)]),
-                                       (9, [(1024, 1), (1024, 33), (512, 1), (256, 1)]),
+@pytest.mark.parametrize("n,configs", [(4, [(128, 1025), (128, 1)]), (5, [(256, 1025), (256, 1)]), (6, [(384, 1025), (384, 1)]),
+                                       (7, [(512, 1025), (512, 1)]),
+                                       (8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9),
+                                           (768, 33), (768, 1025), (768, 2049), (768, 3073), (256, 1025)]),
+                                       (9, [(1024, 2049), (1024, 1), (1024, 33), (512, 1), (256, 1), (1024, 1025), (512, 1025)]),
                                        (10, [(512, 1), (448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
                                              (448, 0), (448, 5), (512, 0), (384, 1), (448, 33), (704, 33), (704, 65),
-                                             (448, 65), (704, 69), (256, 1), (256, 69), (256, 37)]),
+                                             (448, 65), (704, 69), (256, 1), (256, 69), (256, 37), (448, 513), (448, 1025),
+                                             (448, 1537), (512, 1025), (448, 1057), (512, 1057), (512, 1089)]),
                                        (11, [(256, 165), (896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
-                                             (896, 197), (576, 197), (256, 197)]),
+                                             (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221)]),
                                        (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6), (768, 194), (768, 198),
                                              (1024, 198), (576, 198), (256, 2), (256, 198)])])
 def test_persistent_variants_bitwise(n, configs):
