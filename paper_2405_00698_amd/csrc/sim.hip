@@ -229,12 +229,15 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 // issued back to back with at most LAG + 1 outstanding; the read LAG places
 // earlier is waited for by keeping its .w alive, the last LAG ones where their
 // direction's arithmetic needs them anyway.  LAG 0 waits for each read before
-// issuing the next.
+// issuing the next.  LAGB, when not negative, sets the backward-spring reads'
+// lag apart from the forward ones'.
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
-          int VOX = 0, bool SBX = false, int LAG = 0>
+          int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    constexpr int LB = LAGB < 0 ? LAG : LAGB;
     static_assert(VOX == 0 || VAR != 0, "voxel-rebuilt parameters need an exchange variant");
-    static_assert(LAG == 0 || VAR == 1, "pipelined reads need the one-chunk exchange (constant direction indices)");
+    static_assert((LAG == 0 && LB == 0) || VAR == 1,
+                  "pipelined reads need the one-chunk exchange (constant direction indices)");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
@@ -480,11 +483,11 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             float cfv[NDIR], Wk[NDIR];
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
-                                if constexpr (WIDE && LAG > 0) {
+                                if constexpr (WIDE && LB > 0) {
                                     const float4 q = xs[PAD - dir_off(d, N)];
                                     Y[d] = make_float3(q.x, q.y, q.z);
                                     Wk[d] = q.w;
-                                    if (d - LAG >= d0) keep_w(Wk[d - LAG >= 0 ? d - LAG : 0]);
+                                    if (d - LB >= d0) keep_w(Wk[d - LB >= 0 ? d - LB : 0]);
                                 } else {
                                     Y[d] = ldx<WIDE>(xs + (PAD - dir_off(d, N)));
                                 }
@@ -492,8 +495,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             }
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
-                                if constexpr (WIDE && LAG > 0) {
-                                    if (d + LAG >= d1) keep_w(Wk[d]);
+                                if constexpr (WIDE && LB > 0) {
+                                    if (d + LB >= d1) keep_w(Wk[d]);
                                 }
                                 const float ex = Y[d].x - xr[k].x, ey = Y[d].y - xr[k].y, ez = Y[d].z - xr[k].z;
                                 Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
@@ -677,6 +680,20 @@ struct PersistEntry {
             k_persist<NN + 1, BS, VAR, F, false, false, true, false, 0, false, LG>,                          \
             k_persist<NN + 1, BS, VAR, F, true, false, true, false, 0, false, LG>, lds_bytes<NN + 1, BS, VAR>() \
     }
+// separate backward lag: + 4096 * (LB + 1)
+#define SR_PLB(NN, BS, F, LF, LB)                                                                          \
+    {                                                                                                        \
+        NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1),                                                      \
+            k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB>,                        \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB>, lds_bytes<NN + 1, BS, 1>() \
+    }
+#define SR_PVLB(NN, BS, VOX, SBX, F, LF, LB)                                                              \
+    {                                                                                                        \
+        NN, BS, 1 + 4 * F + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1),                               \
+            k_persist<NN + 1, BS, 1, F, false, false, true, false, VOX, SBX, LF, LB>,                        \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, VOX, SBX, LF, LB>,                         \
+            lds_bytes<NN + 1, BS, 1, false, VOX, SBX>()                                                      \
+    }
 #define SR_PVL(NN, BS, VAR, VOX, SBX, F, LG)                                                              \
     {                                                                                                        \
         NN, BS, VAR + 4 * F + 32 * VOX + 128 * SBX + 256 * LG,                                               \
@@ -698,7 +715,7 @@ struct PersistEntry {
 // population).
 const PersistEntry kPersist[] = {
     SR_PL(4, 128, 1, 0, 4),   SR_PL(5, 256, 1, 0, 4),   SR_PL(6, 384, 1, 0, 4),   SR_PL(7, 512, 1, 0, 4),
-    SR_PL(8, 768, 1, 0, 4),   SR_PL(9, 1024, 1, 0, 8),  SR_PE(10, 448, 1, 0, 1),  SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PL(8, 768, 1, 0, 12),  SR_PLB(9, 1024, 0, 12, 0), SR_PLB(10, 512, 0, 12, 0), SR_PVL(11, 256, 1, 2, 1, 1, 4),
     SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
@@ -721,9 +738,15 @@ const PersistEntry kPersist[] = {
     SR_PV(10, 256, 1, 2, 0, 1),  SR_PV(10, 256, 1, 1, 0, 1),  SR_PV(11, 256, 1, 2, 1, 1),  SR_PV(12, 256, 2, 2, 1, 1),
     // pipelined neighbour reads
     SR_PL(10, 448, 1, 0, 2),  SR_PL(10, 448, 1, 0, 4),  SR_PL(10, 448, 1, 0, 6),  SR_PL(10, 512, 1, 0, 4),
-    SR_PL(9, 1024, 1, 0, 4),  SR_PL(11, 256, 1, 0, 4),  SR_PL(8, 768, 1, 0, 8),   SR_PL(8, 768, 1, 0, 12),
+    SR_PL(9, 1024, 1, 0, 4),  SR_PL(11, 256, 1, 0, 4),  SR_PL(8, 768, 1, 0, 8),   SR_PL(8, 768, 1, 0, 4),
+    SR_PL(9, 1024, 1, 0, 8),  SR_PE(10, 448, 1, 0, 1),
     SR_PL(9, 512, 1, 0, 4),   SR_PL(8, 256, 1, 0, 4),   SR_PVL(10, 448, 1, 1, 0, 0, 4),  SR_PVL(10, 512, 1, 1, 0, 0, 4),
     SR_PVL(10, 512, 1, 2, 0, 0, 4),  SR_PVL(11, 256, 1, 1, 1, 1, 4),
+    SR_PLB(10, 448, 0, 4, 0),  SR_PLB(10, 448, 0, 2, 0),  SR_PLB(10, 448, 0, 6, 0),  SR_PLB(10, 448, 0, 8, 0),
+    SR_PLB(10, 448, 0, 12, 0), SR_PLB(10, 512, 0, 4, 0),  SR_PLB(10, 512, 0, 6, 0),  SR_PLB(10, 448, 1, 4, 0),
+    SR_PLB(10, 448, 0, 12, 2), SR_PLB(10, 448, 1, 12, 0), SR_PLB(8, 768, 0, 12, 4),
+    SR_PLB(9, 1024, 0, 12, 8), SR_PVLB(11, 256, 2, 1, 1, 12, 4),
+    SR_PVLB(11, 256, 2, 1, 1, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 4, 0),
     // spring dashpots (Table II model)
     SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
     SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
@@ -734,17 +757,17 @@ const PersistEntry kPersist[] = {
 
 #define SR_REC(NN, BS, VAR) \
     { NN, BS, VAR, k_persist<NN + 1, BS, VAR, false, false, true>, k_persist<NN + 1, BS, VAR, false, true, true>, 0 }
-#define SR_RECL(NN, BS, LG)                                                                      \
-    {                                                                                            \
-        NN, BS, 1 + 256 * LG, k_persist<NN + 1, BS, 1, false, false, true, true, false, 0, false, LG>, \
-            k_persist<NN + 1, BS, 1, false, true, true, true, false, 0, false, LG>, 0            \
+#define SR_RECL(NN, BS, LF, LB)                                                                      \
+    {                                                                                                \
+        NN, BS, 1, k_persist<NN + 1, BS, 1, false, false, true, true, false, 0, false, LF, LB>,     \
+            k_persist<NN + 1, BS, 1, false, true, true, true, false, 0, false, LF, LB>, 0            \
     }
 
 // recording forms (used to recompute checkpointed segments for the adjoint)
 const PersistEntry kRec[] = {
-    SR_REC(1, 64, 1),     SR_REC(2, 64, 1),     SR_REC(3, 64, 1),     SR_RECL(4, 128, 4),  SR_RECL(5, 256, 4),
-    SR_RECL(6, 384, 4),   SR_RECL(7, 512, 4),   SR_RECL(8, 768, 4),   SR_RECL(9, 1024, 8), SR_REC(10, 448, 1),
-    SR_REC(11, 896, 1),   SR_REC(12, 768, 2),
+    SR_REC(1, 64, 1),          SR_REC(2, 64, 1),          SR_REC(3, 64, 1),           SR_RECL(4, 128, 4, 4),
+    SR_RECL(5, 256, 4, 4),     SR_RECL(6, 384, 4, 4),     SR_RECL(7, 512, 4, 4),      SR_RECL(8, 768, 12, 12),
+    SR_RECL(9, 1024, 12, 0),   SR_RECL(10, 512, 12, 0),   SR_REC(11, 896, 1),         SR_REC(12, 768, 2),
 };
 
 const PersistEntry *find_persist(const PersistCfg &cfg) {

@@ -109,14 +109,18 @@ def test_plain_and_persistent_agree_bitwise():
 @pytest.mark.parametrize("n,configs", [(4, [(128, 1025), (128, 1)]), (5, [(256, 1025), (256, 1)]), (6, [(384, 1025), (384, 1)]),
                                        (7, [(512, 1025), (512, 1)]),
                                        (8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9),
-                                           (768, 33), (768, 1025), (768, 2049), (768, 3073), (256, 1025)]),
-                                       (9, [(1024, 2049), (1024, 1), (1024, 33), (512, 1), (256, 1), (1024, 1025), (512, 1025)]),
+                                           (768, 33), (768, 1025), (768, 2049), (768, 3073), (256, 1025), (768, 23553)]),
+                                       (9, [(1024, 2049), (1024, 1), (1024, 33), (512, 1), (256, 1), (1024, 1025), (512, 1025), (1024, 39937),
+                                           (1024, 7169)]),
                                        (10, [(512, 1), (448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
                                              (448, 0), (448, 5), (512, 0), (384, 1), (448, 33), (704, 33), (704, 65),
                                              (448, 65), (704, 69), (256, 1), (256, 69), (256, 37), (448, 513), (448, 1025),
-                                             (448, 1537), (512, 1025), (448, 1057), (512, 1057), (512, 1089)]),
+                                             (448, 1537), (512, 1025), (448, 1057), (512, 1057), (512, 1089), (448, 5121), (448, 4609),
+                                             (448, 5633), (448, 6145), (448, 7169), (512, 5121), (512, 5633), (448, 5125),
+                                             (448, 15361), (512, 7169), (448, 7173)]),
                                        (11, [(256, 165), (896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
-                                             (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221)]),
+                                             (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221), (256, 23749), (256, 7365),
+                                             (256, 5317)]),
                                        (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6), (768, 194), (768, 198),
                                              (1024, 198), (576, 198), (256, 2), (256, 198)])])
 def test_persistent_variants_bitwise(n, configs):
