@@ -715,7 +715,7 @@ struct PersistEntry {
 // population).
 const PersistEntry kPersist[] = {
     SR_PL(4, 128, 1, 0, 4),   SR_PL(5, 256, 1, 0, 4),   SR_PL(6, 384, 1, 0, 4),   SR_PL(7, 512, 1, 0, 4),
-    SR_PL(8, 768, 1, 0, 12),  SR_PLB(9, 1024, 0, 12, 0), SR_PLB(10, 512, 0, 12, 0), SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PLB(8, 768, 0, 12, 4), SR_PLB(9, 1024, 0, 12, 8), SR_PLB(10, 512, 0, 12, 0), SR_PVL(11, 256, 1, 2, 1, 1, 4),
     SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
@@ -744,9 +744,10 @@ const PersistEntry kPersist[] = {
     SR_PVL(10, 512, 1, 2, 0, 0, 4),  SR_PVL(11, 256, 1, 1, 1, 1, 4),
     SR_PLB(10, 448, 0, 4, 0),  SR_PLB(10, 448, 0, 2, 0),  SR_PLB(10, 448, 0, 6, 0),  SR_PLB(10, 448, 0, 8, 0),
     SR_PLB(10, 448, 0, 12, 0), SR_PLB(10, 512, 0, 4, 0),  SR_PLB(10, 512, 0, 6, 0),  SR_PLB(10, 448, 1, 4, 0),
-    SR_PLB(10, 448, 0, 12, 2), SR_PLB(10, 448, 1, 12, 0), SR_PLB(8, 768, 0, 12, 4),
-    SR_PLB(9, 1024, 0, 12, 8), SR_PVLB(11, 256, 2, 1, 1, 12, 4),
+    SR_PLB(10, 448, 0, 12, 2), SR_PLB(10, 448, 1, 12, 0), SR_PL(8, 768, 1, 0, 12),
+    SR_PLB(9, 1024, 0, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 12, 4),
     SR_PVLB(11, 256, 2, 1, 1, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 4, 0),
+    SR_PLB(7, 512, 0, 12, 0), SR_PLB(6, 384, 0, 12, 0), SR_PLB(5, 256, 0, 12, 0), SR_PLB(4, 128, 0, 12, 0),
     // spring dashpots (Table II model)
     SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
     SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),

@@ -106,8 +106,10 @@ def test_plain_and_persistent_agree_bitwise():
     assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
 
 
-@pytest.mark.parametrize("n,configs", [(4, [(128, 1025), (128, 1)]), (5, [(256, 1025), (256, 1)]), (6, [(384, 1025), (384, 1)]),
-                                       (7, [(512, 1025), (512, 1)]),
+@pytest.mark.parametrize("n,configs", [(4, [(128, 1025), (128, 1), (128, 7169)]),
+                                       (5, [(256, 1025), (256, 1), (256, 7169)]),
+                                       (6, [(384, 1025), (384, 1), (384, 7169)]),
+                                       (7, [(512, 1025), (512, 1), (512, 7169)]),
                                        (8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9),
                                            (768, 33), (768, 1025), (768, 2049), (768, 3073), (256, 1025), (768, 23553)]),
                                        (9, [(1024, 2049), (1024, 1), (1024, 33), (512, 1), (256, 1), (1024, 1025), (512, 1025), (1024, 39937),
