@@ -397,20 +397,28 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
                             float3 Y[NDIR], VY[DASH ? NDIR : 1];
-                            float Wk[NDIR];
+                            float Wk[NDIR], Wv[DASH ? NDIR : 1];
                             if constexpr (WIDE && LAG > 0) {
 #pragma unroll
                                 for (int d = d0; d < d1; ++d) {
                                     const float4 q = xs[PAD + dir_off(d, N)];
                                     Y[d] = make_float3(q.x, q.y, q.z);
                                     Wk[d] = q.w;
-                                    if (d - LAG >= d0) keep_w(Wk[d - LAG >= 0 ? d - LAG : 0]);
+                                    if constexpr (DASH) {
+                                        const float4 u = vb[s + PAD + dir_off(d, N)];
+                                        VY[DASH ? d : 0] = make_float3(u.x, u.y, u.z);
+                                        Wv[DASH ? d : 0] = u.w;
+                                    }
+                                    if (d - LAG >= d0) {
+                                        keep_w(Wk[d - LAG >= 0 ? d - LAG : 0]);
+                                        if constexpr (DASH) keep_w(Wv[DASH && d - LAG >= 0 ? d - LAG : 0]);
+                                    }
                                 }
                             } else {
 #pragma unroll
                                 for (int d = d0; d < d1; ++d) Y[d] = ldx<WIDE>(xs + (PAD + dir_off(d, N)));
                             }
-                            if constexpr (DASH) {
+                            if constexpr (DASH && !(WIDE && LAG > 0)) {
 #pragma unroll
                                 for (int d = d0; d < d1; ++d) VY[DASH ? d : 0] = ldx<WIDE>(vb + s + (PAD + dir_off(d, N)));
                             }
@@ -428,7 +436,10 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
                                 if constexpr (WIDE && LAG > 0) {
-                                    if (d + LAG >= d1) keep_w(Wk[d]);
+                                    if (d + LAG >= d1) {
+                                        keep_w(Wk[d]);
+                                        if constexpr (DASH) keep_w(Wv[DASH ? d : 0]);
+                                    }
                                 }
                                 const float dx = Y[d].x - xr[k].x, dy = Y[d].y - xr[k].y, dz = Y[d].z - xr[k].z;
                                 float kk, al, be, cd;
@@ -702,11 +713,19 @@ struct PersistEntry {
             lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()                                                    \
     }
 // dashpot kernels carry the phase plane always (with a zero plane the results
-// are the same bits as without it)
+// are the same bits as without it); SR_PDL with pipelined reads (positions and
+// velocities)
 #define SR_PD(NN, BS, VAR)                                                                              \
     {                                                                                                   \
         NN, BS, VAR + 16, k_persist<NN + 1, BS, VAR, false, true, false, true, true>,                   \
             k_persist<NN + 1, BS, VAR, false, true, false, true, true>, lds_bytes<NN + 1, BS, VAR, true>() \
+    }
+#define SR_PDL(NN, BS, LF, LB)                                                                         \
+    {                                                                                                    \
+        NN, BS, 1 + 16 + 256 * LF + 4096 * (LB + 1),                                                     \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB>,                  \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB>,                  \
+            lds_bytes<NN + 1, BS, 1, true>()                                                             \
     }
 
 // The first entry of each side is its default configuration, the first one
@@ -749,11 +768,14 @@ const PersistEntry kPersist[] = {
     SR_PVLB(11, 256, 2, 1, 1, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 4, 0),
     SR_PLB(7, 512, 0, 12, 0), SR_PLB(6, 384, 0, 12, 0), SR_PLB(5, 256, 0, 12, 0), SR_PLB(4, 128, 0, 12, 0),
     // spring dashpots (Table II model)
+    SR_PDL(4, 128, 4, 4),   SR_PDL(5, 256, 4, 4),   SR_PDL(6, 384, 4, 4),   SR_PDL(7, 512, 4, 4),
+    SR_PDL(8, 768, 4, 4),   SR_PD(9, 1024, 1),
     SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
     SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
-    SR_PD(7, 512, 0),   SR_PD(8, 768, 1),   SR_PD(8, 768, 0),    SR_PD(9, 512, 1),   SR_PD(9, 1024, 1),
+    SR_PD(7, 512, 0),   SR_PD(8, 768, 1),   SR_PD(8, 768, 0),    SR_PD(9, 512, 1),
     SR_PD(9, 512, 0),   SR_PD(10, 512, 1),  SR_PD(10, 448, 1),   SR_PD(10, 704, 1),  SR_PD(11, 512, 2),
     SR_PD(11, 576, 2),  SR_PD(11, 896, 2),  SR_PD(12, 512, 0),   SR_PD(12, 768, 0),
+    SR_PDL(8, 768, 12, 0),  SR_PDL(5, 256, 12, 0),
 };
 
 #define SR_REC(NN, BS, VAR) \

@@ -100,7 +100,7 @@ def test_table2_contact_and_friction_exercised(orc):
         np.testing.assert_allclose(vs[r], v, atol=1e-3 * max(np.abs(v).max(), 1e-3))
 
 
-@pytest.mark.parametrize("n", [3, 5, 8, 9, 10, 11, 12])
+@pytest.mark.parametrize("n", [3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
 def test_dashpot_kernels_bitwise_equal_per_step_kernel(n):
     from paper_2405_00698_amd import api
     sides = [n] * 3
