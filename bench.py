@@ -45,9 +45,9 @@ def measured_traffic(kernel_cfg, sim_steps, key="hbm_bytes_per_launch"):
     h = hashlib.sha256()
     for f in d["source_files"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != d["source_sha256"] or d["launch_steps"] != sim_steps or d["kernel"] != kernel_cfg:
+    if h.hexdigest() != d["source_sha256"] or d["launch_steps"] != sim_steps or kernel_cfg not in d["kernels"]:
         return None
-    return d.get(key)
+    return d["kernels"][kernel_cfg].get(key)
 
 
 def parse():
@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the per-step-launch baseline and the adjoint/forward ratio")
     ap.add_argument("--no-tune", action="store_true", help="keep the default step-kernel configuration")
+    ap.add_argument("--kernel", default=None,
+                    help="BLOCK,VARIANT: run the uniform workload with this step-kernel configuration (no tuning)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (HBM counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -196,7 +198,10 @@ def main():
         gacfg = GAConfig()
 
     tuned = None
-    if not args.no_tune:
+    if args.kernel:
+        b, v = (int(q) for q in args.kernel.split(","))
+        P.set_persist_variant(args.side, b, v)
+    elif not args.no_tune:
         # pick the fastest compiled step-kernel configuration for this population (cached)
         from paper_2405_00698_amd import tune
         P.build_from_genomes(Gt[0], Bt, prec)

@@ -230,10 +230,16 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 // earlier is waited for by keeping its .w alive, the last LAG ones where their
 // direction's arithmetic needs them anyway.  LAG 0 waits for each read before
 // issuing the next.  LAGB, when not negative, sets the backward-spring reads'
-// lag apart from the forward ones'.
+// lag apart from the forward ones'.  BSWP software-pipelines the backward
+// springs instead: direction d's arithmetic follows the issue of direction
+// d + LAGB's reads, so only a window of reads is held in registers; FSWP does
+// the same for the forward springs with window LAG (and stores each
+// coefficient as soon as it is computed).
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
-          int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1>
+          int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    static_assert(!FSWP || (WIDE && VAR == 1 && VOX == 0 && !DASH && LAG > 0),
+                  "the software-pipelined forward springs are a form of the plain one-chunk exchange");
     constexpr int LB = LAGB < 0 ? LAG : LAGB;
     static_assert(VOX == 0 || VAR != 0, "voxel-rebuilt parameters need an exchange variant");
     static_assert((LAG == 0 && LB == 0) || VAR == 1,
@@ -396,6 +402,25 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             // addresses are one base plus non-negative immediates
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
+                            if constexpr (FSWP) {
+                                float4 Q[NDIR];
+#pragma unroll
+                                for (int d = d0; d < d1 && d < d0 + LAG; ++d) Q[d] = xs[PAD + dir_off(d, N)];
+#pragma unroll
+                                for (int d = d0; d < d1; ++d) {
+                                    const int e = d + LAG < d1 ? d + LAG : d0;
+                                    if (d + LAG < d1) Q[e] = xs[PAD + dir_off(e, N)];
+                                    keep_w(Q[d].w);
+                                    const float dx = Q[d].x - xr[k].x, dy = Q[d].y - xr[k].y, dz = Q[d].z - xr[k].z;
+                                    const float kk = pk[k][d];
+                                    const float cf = spring_coef<PHASE>(kk, kk * L0d(c, d), pa[k][d], PHASE ? pb[k][d] : 0.f,
+                                                                        sct.x, sct.y, len2(dx, dy, dz));
+                                    cs[(d - d0) * CL + PAD] = cf;
+                                    Ff[k].x = fmaf(cf, dx, Ff[k].x);
+                                    Ff[k].y = fmaf(cf, dy, Ff[k].y);
+                                    Ff[k].z = fmaf(cf, dz, Ff[k].z);
+                                }
+                            } else {
                             float3 Y[NDIR], VY[DASH ? NDIR : 1];
                             float Wk[NDIR], Wv[DASH ? NDIR : 1];
                             if constexpr (WIDE && LAG > 0) {
@@ -480,6 +505,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             }
 #pragma unroll
                             for (int d = d0; d < d1; ++d) cs[(d - d0) * CL + PAD] = cfv[d];
+                            }
                         }
                         if (FENCE) __builtin_amdgcn_sched_barrier(0);
                     }
@@ -492,6 +518,27 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             const float *cs = coef + s;
                             float3 Y[NDIR];
                             float cfv[NDIR], Wk[NDIR];
+                            if constexpr (WIDE && BSWP) {
+                                float4 Q[NDIR];
+#pragma unroll
+                                for (int d = d0; d < d1 && d < d0 + LB; ++d) {
+                                    Q[d] = xs[PAD - dir_off(d, N)];
+                                    cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
+                                }
+#pragma unroll
+                                for (int d = d0; d < d1; ++d) {
+                                    const int e = d + LB < d1 ? d + LB : d0;
+                                    if (d + LB < d1) {
+                                        Q[e] = xs[PAD - dir_off(e, N)];
+                                        cfv[e] = cs[(e - d0) * CL + (PAD - dir_off(e, N))];
+                                    }
+                                    keep_w(Q[d].w);
+                                    const float ex = Q[d].x - xr[k].x, ey = Q[d].y - xr[k].y, ez = Q[d].z - xr[k].z;
+                                    Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
+                                    Fb[k].y = fmaf(cfv[d], ey, Fb[k].y);
+                                    Fb[k].z = fmaf(cfv[d], ez, Fb[k].z);
+                                }
+                            } else {
 #pragma unroll
                             for (int d = d0; d < d1; ++d) {
                                 if constexpr (WIDE && LB > 0) {
@@ -513,6 +560,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                 Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
                                 Fb[k].y = fmaf(cfv[d], ey, Fb[k].y);
                                 Fb[k].z = fmaf(cfv[d], ez, Fb[k].z);
+                            }
                             }
                         }
                         if (FENCE) __builtin_amdgcn_sched_barrier(0);
@@ -698,6 +746,21 @@ struct PersistEntry {
             k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB>,                        \
             k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB>, lds_bytes<NN + 1, BS, 1>() \
     }
+// software-pipelined backward springs: + 131072
+#define SR_PLS(NN, BS, F, LF, LB)                                                                          \
+    {                                                                                                        \
+        NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072,                                             \
+            k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, true>,                  \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, true>, lds_bytes<NN + 1, BS, 1>() \
+    }
+// software-pipelined forward springs: + 262144
+#define SR_PLF(NN, BS, F, LF, LB, BSW)                                                                     \
+    {                                                                                                        \
+        NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072 * BSW + 262144,                              \
+            k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, BSW, true>,             \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, BSW, true>,              \
+            lds_bytes<NN + 1, BS, 1>()                                                                       \
+    }
 #define SR_PVLB(NN, BS, VOX, SBX, F, LF, LB)                                                              \
     {                                                                                                        \
         NN, BS, 1 + 4 * F + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1),                               \
@@ -733,8 +796,11 @@ struct PersistEntry {
 // (the fastest measured: 4096 robots of 10^3; 11^3 and 12^3 robots of an uneven
 // population).
 const PersistEntry kPersist[] = {
+    SR_PLF(4, 128, 0, 3, 3, 1),  SR_PLF(5, 256, 0, 3, 3, 1),  SR_PLF(6, 384, 0, 3, 3, 1),  SR_PLF(7, 512, 0, 3, 3, 1),
     SR_PL(4, 128, 1, 0, 4),   SR_PL(5, 256, 1, 0, 4),   SR_PL(6, 384, 1, 0, 4),   SR_PL(7, 512, 1, 0, 4),
-    SR_PLB(8, 768, 0, 12, 4), SR_PLB(9, 1024, 0, 12, 8), SR_PLB(10, 512, 0, 12, 0), SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLF(10, 448, 0, 3, 3, 1), SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PLS(10, 512, 0, 12, 3),
+    SR_PLB(8, 768, 0, 12, 4), SR_PLB(9, 1024, 0, 12, 8),
     SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
@@ -767,6 +833,10 @@ const PersistEntry kPersist[] = {
     SR_PLB(9, 1024, 0, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 12, 4),
     SR_PVLB(11, 256, 2, 1, 1, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 4, 0),
     SR_PLB(7, 512, 0, 12, 0), SR_PLB(6, 384, 0, 12, 0), SR_PLB(5, 256, 0, 12, 0), SR_PLB(4, 128, 0, 12, 0),
+    SR_PLS(10, 512, 0, 12, 2), SR_PLS(10, 512, 0, 12, 4), SR_PLS(10, 448, 0, 12, 3), SR_PLS(8, 768, 0, 12, 4),
+    SR_PLS(10, 512, 0, 12, 1), SR_PLS(10, 448, 0, 12, 2), SR_PLB(10, 512, 0, 12, 0),
+    SR_PLF(10, 512, 0, 2, 2, 1), SR_PLF(10, 512, 0, 3, 3, 1), SR_PLF(10, 512, 0, 4, 2, 1),
+    SR_PLF(10, 512, 0, 6, 3, 1), SR_PLS(9, 1024, 0, 12, 4),   SR_PLF(8, 256, 0, 3, 3, 1),  SR_PLF(9, 512, 0, 3, 3, 1),
     // spring dashpots (Table II model)
     SR_PDL(4, 128, 4, 4),   SR_PDL(5, 256, 4, 4),   SR_PDL(6, 384, 4, 4),   SR_PDL(7, 512, 4, 4),
     SR_PDL(8, 768, 4, 4),   SR_PD(9, 1024, 1),
@@ -780,17 +850,17 @@ const PersistEntry kPersist[] = {
 
 #define SR_REC(NN, BS, VAR) \
     { NN, BS, VAR, k_persist<NN + 1, BS, VAR, false, false, true>, k_persist<NN + 1, BS, VAR, false, true, true>, 0 }
-#define SR_RECL(NN, BS, LF, LB)                                                                      \
-    {                                                                                                \
-        NN, BS, 1, k_persist<NN + 1, BS, 1, false, false, true, true, false, 0, false, LF, LB>,     \
-            k_persist<NN + 1, BS, 1, false, true, true, true, false, 0, false, LF, LB>, 0            \
+#define SR_RECL(NN, BS, LF, LB, SW)                                                                      \
+    {                                                                                                    \
+        NN, BS, 1, k_persist<NN + 1, BS, 1, false, false, true, true, false, 0, false, LF, LB, SW, SW>, \
+            k_persist<NN + 1, BS, 1, false, true, true, true, false, 0, false, LF, LB, SW, SW>, 0        \
     }
 
 // recording forms (used to recompute checkpointed segments for the adjoint)
 const PersistEntry kRec[] = {
-    SR_REC(1, 64, 1),          SR_REC(2, 64, 1),          SR_REC(3, 64, 1),           SR_RECL(4, 128, 4, 4),
-    SR_RECL(5, 256, 4, 4),     SR_RECL(6, 384, 4, 4),     SR_RECL(7, 512, 4, 4),      SR_RECL(8, 768, 12, 12),
-    SR_RECL(9, 1024, 12, 0),   SR_RECL(10, 512, 12, 0),   SR_REC(11, 896, 1),         SR_REC(12, 768, 2),
+    SR_REC(1, 64, 1),            SR_REC(2, 64, 1),            SR_REC(3, 64, 1),            SR_RECL(4, 128, 4, 4, false),
+    SR_RECL(5, 256, 4, 4, false), SR_RECL(6, 384, 4, 4, false), SR_RECL(7, 512, 4, 4, false), SR_RECL(8, 768, 3, 3, true),
+    SR_RECL(9, 1024, 3, 3, true), SR_RECL(10, 512, 3, 3, true), SR_REC(11, 896, 1),           SR_REC(12, 768, 2),
 };
 
 const PersistEntry *find_persist(const PersistCfg &cfg) {

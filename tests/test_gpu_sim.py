@@ -106,20 +106,22 @@ def test_plain_and_persistent_agree_bitwise():
     assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
 
 
-@pytest.mark.parametrize("n,configs", [(4, [(128, 1025), (128, 1), (128, 7169)]),
-                                       (5, [(256, 1025), (256, 1), (256, 7169)]),
-                                       (6, [(384, 1025), (384, 1), (384, 7169)]),
-                                       (7, [(512, 1025), (512, 1), (512, 7169)]),
+@pytest.mark.parametrize("n,configs", [(4, [(128, 1025), (128, 1), (128, 7169), (128, 410369)]),
+                                       (5, [(256, 1025), (256, 1), (256, 7169), (256, 410369)]),
+                                       (6, [(384, 1025), (384, 1), (384, 7169), (384, 410369)]),
+                                       (7, [(512, 1025), (512, 1), (512, 7169), (512, 410369)]),
                                        (8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9),
-                                           (768, 33), (768, 1025), (768, 2049), (768, 3073), (256, 1025), (768, 23553)]),
+                                           (768, 33), (768, 1025), (768, 2049), (768, 3073), (256, 1025), (768, 23553), (768, 154625), (768, 410369), (256, 410369)]),
                                        (9, [(1024, 2049), (1024, 1), (1024, 33), (512, 1), (256, 1), (1024, 1025), (512, 1025), (1024, 39937),
-                                           (1024, 7169)]),
+                                           (1024, 7169), (1024, 154625), (1024, 410369), (512, 410369)]),
                                        (10, [(512, 1), (448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
                                              (448, 0), (448, 5), (512, 0), (384, 1), (448, 33), (704, 33), (704, 65),
                                              (448, 65), (704, 69), (256, 1), (256, 69), (256, 37), (448, 513), (448, 1025),
                                              (448, 1537), (512, 1025), (448, 1057), (512, 1057), (512, 1089), (448, 5121), (448, 4609),
                                              (448, 5633), (448, 6145), (448, 7169), (512, 5121), (512, 5633), (448, 5125),
-                                             (448, 15361), (512, 7169), (448, 7173)]),
+                                             (448, 15361), (512, 7169), (448, 7173), (512, 146433), (512, 154625),
+                                             (448, 150529), (512, 142337), (448, 146433), (512, 150529), (512, 406017),
+                                             (512, 410369), (512, 406529), (448, 410369), (512, 411137)]),
                                        (11, [(256, 165), (896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
                                              (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221), (256, 23749), (256, 7365),
                                              (256, 5317)]),
