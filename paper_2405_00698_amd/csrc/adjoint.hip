@@ -118,10 +118,37 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         }
         __syncthreads();
 
+        // the recorded state of each step is read one step ahead, so the global
+        // loads are in flight during the previous step's spring part
+        float4 XRn[NPT], VPn[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            if (pres[k] && A.n_steps > 0) {
+                XRn[k] = A.rec_x[rbase + (size_t)(A.n_steps - 1) * SL + s];
+                VPn[k] = A.rec_v[rbase + (size_t)(A.n_steps - 1) * SL + s];
+            } else {
+                XRn[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                VPn[k] = XRn[k];
+            }
+        }
+        float2 sc_next = A.n_steps > 0 ? A.sc[A.n_steps - 1] : make_float2(0.f, 0.f);
         for (int t = A.n_steps - 1; t >= 0; --t) {
             const int b = XCH ? 0 : (t & 1);
             if (XCH) __syncthreads();  // the previous step's readers are done with the buffers
-            const float2 sct = A.sc[t];
+            const float2 sct = sc_next;
+            if (t > 0) sc_next = A.sc[t - 1];
+            float4 XRc[NPT], VPc[NPT];
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int s = tid + k * BS;
+                XRc[k] = XRn[k];
+                VPc[k] = VPn[k];
+                if (pres[k] && t > 0) {
+                    XRn[k] = A.rec_x[rbase + (size_t)(t - 1) * SL + s];
+                    VPn[k] = A.rec_v[rbase + (size_t)(t - 1) * SL + s];
+                }
+            }
             float3 Xr[NPT], LF[NPT];
             // node-local part of the reverse step
 #pragma unroll
@@ -130,8 +157,8 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 if (s >= SL) continue;
                 float3 X = X0[k], lF = make_float3(0.f, 0.f, 0.f);
                 if (pres[k]) {
-                    const float4 XR = A.rec_x[rbase + (size_t)t * SL + s];
-                    const float4 VP = A.rec_v[rbase + (size_t)t * SL + s];
+                    const float4 XR = XRc[k];
+                    const float4 VP = VPc[k];
                     X = make_float3(XR.x, XR.y, XR.z);
                     float ux = c.damping * fmaf(c.dt, lx[k].x, lv[k].x);
                     float uy = c.damping * fmaf(c.dt, lx[k].y, lv[k].y);

@@ -238,7 +238,7 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
           int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
-    static_assert(!FSWP || (WIDE && VAR == 1 && VOX == 0 && !DASH && LAG > 0),
+    static_assert(!FSWP || (WIDE && VAR == 1 && !DASH && LAG > 0),
                   "the software-pipelined forward springs are a form of the plain one-chunk exchange");
     constexpr int LB = LAGB < 0 ? LAG : LAGB;
     static_assert(VOX == 0 || VAR != 0, "voxel-rebuilt parameters need an exchange variant");
@@ -404,6 +404,14 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             float *cs = coef + s;
                             if constexpr (FSWP) {
                                 float4 Q[NDIR];
+                                float4 Vx[VOX > 0 ? 8 : 1];
+                                if constexpr (VOX > 0) {
+                                    // re-read every step (see below)
+                                    int vo = PAD + s;
+                                    __asm__ volatile("" : "+v"(vo));
+#pragma unroll
+                                    for (int i = 0; i < 8; ++i) Vx[i] = vox4(vv[vo + vox_off(i, N)]);
+                                }
 #pragma unroll
                                 for (int d = d0; d < d1 && d < d0 + LAG; ++d) Q[d] = xs[PAD + dir_off(d, N)];
 #pragma unroll
@@ -412,9 +420,26 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                     if (d + LAG < d1) Q[e] = xs[PAD + dir_off(e, N)];
                                     keep_w(Q[d].w);
                                     const float dx = Q[d].x - xr[k].x, dy = Q[d].y - xr[k].y, dz = Q[d].z - xr[k].z;
-                                    const float kk = pk[k][d];
-                                    const float cf = spring_coef<PHASE>(kk, kk * L0d(c, d), pa[k][d], PHASE ? pb[k][d] : 0.f,
-                                                                        sct.x, sct.y, len2(dx, dy, dz));
+                                    float kk, al, be;
+                                    if (from_vox(VOX, d)) {
+                                        float4 sm = Vx[VOX > 0 ? vox_idx(d, 0) : 0];
+#pragma unroll
+                                        for (int i = 1; i < vox_cnt(d); ++i) {
+                                            const float4 u = Vx[VOX > 0 ? vox_idx(d, i) : 0];
+                                            sm.x = add_nf(sm.x, u.x);
+                                            sm.y = add_nf(sm.y, u.y);
+                                            if (PHASE) sm.z = add_nf(sm.z, u.z);
+                                        }
+                                        kk = sm.x;
+                                        al = mul_nf(sm.y, L0d(c, d));
+                                        be = PHASE ? mul_nf(sm.z, L0d(c, d)) : 0.f;
+                                    } else {
+                                        kk = pk[k][d];
+                                        al = pa[k][d];
+                                        be = PHASE ? pb[k][d] : 0.f;
+                                    }
+                                    const float cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y,
+                                                                        len2(dx, dy, dz));
                                     cs[(d - d0) * CL + PAD] = cf;
                                     Ff[k].x = fmaf(cf, dx, Ff[k].x);
                                     Ff[k].y = fmaf(cf, dy, Ff[k].y);
@@ -761,6 +786,13 @@ struct PersistEntry {
             k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, BSW, true>,              \
             lds_bytes<NN + 1, BS, 1>()                                                                       \
     }
+#define SR_PVLF(NN, BS, VOX, SBX, F, LF, LB, BSW)                                                            \
+    {                                                                                                        \
+        NN, BS, 1 + 4 * F + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1) + 131072 * BSW + 262144,       \
+            k_persist<NN + 1, BS, 1, F, false, false, true, false, VOX, SBX, LF, LB, BSW, true>,             \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, VOX, SBX, LF, LB, BSW, true>,              \
+            lds_bytes<NN + 1, BS, 1, false, VOX, SBX>()                                                      \
+    }
 #define SR_PVLB(NN, BS, VOX, SBX, F, LF, LB)                                                              \
     {                                                                                                        \
         NN, BS, 1 + 4 * F + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1),                               \
@@ -837,6 +869,7 @@ const PersistEntry kPersist[] = {
     SR_PLS(10, 512, 0, 12, 1), SR_PLS(10, 448, 0, 12, 2), SR_PLB(10, 512, 0, 12, 0),
     SR_PLF(10, 512, 0, 2, 2, 1), SR_PLF(10, 512, 0, 3, 3, 1), SR_PLF(10, 512, 0, 4, 2, 1),
     SR_PLF(10, 512, 0, 6, 3, 1), SR_PLS(9, 1024, 0, 12, 4),   SR_PLF(8, 256, 0, 3, 3, 1),  SR_PLF(9, 512, 0, 3, 3, 1),
+    SR_PVLF(11, 896, 2, 1, 1, 3, 3, 1), SR_PVLF(11, 256, 1, 1, 1, 3, 3, 1),
     // spring dashpots (Table II model)
     SR_PDL(4, 128, 4, 4),   SR_PDL(5, 256, 4, 4),   SR_PDL(6, 384, 4, 4),   SR_PDL(7, 512, 4, 4),
     SR_PDL(8, 768, 4, 4),   SR_PD(9, 1024, 1),

@@ -124,7 +124,7 @@ def test_plain_and_persistent_agree_bitwise():
                                              (512, 410369), (512, 406529), (448, 410369), (512, 411137)]),
                                        (11, [(256, 165), (896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
                                              (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221), (256, 23749), (256, 7365),
-                                             (256, 5317)]),
+                                             (256, 5317), (256, 410533), (896, 410565)]),
                                        (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6), (768, 194), (768, 198),
                                              (1024, 198), (576, 198), (256, 2), (256, 198)])])
 def test_persistent_variants_bitwise(n, configs):
