@@ -413,9 +413,11 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                     for (int i = 0; i < 8; ++i) Vx[i] = vox4(vv[vo + vox_off(i, N)]);
                                 }
 #pragma unroll
-                                for (int d = d0; d < d1 && d < d0 + LAG; ++d) Q[d] = xs[PAD + dir_off(d, N)];
+                                for (int d = 0; d < NDIR; ++d)
+                                    if (d >= d0 && d < d1 && d < d0 + LAG) Q[d] = xs[PAD + dir_off(d, N)];
 #pragma unroll
-                                for (int d = d0; d < d1; ++d) {
+                                for (int d = 0; d < NDIR; ++d) {
+                                    if (d < d0 || d >= d1) continue;
                                     const int e = d + LAG < d1 ? d + LAG : d0;
                                     if (d + LAG < d1) Q[e] = xs[PAD + dir_off(e, N)];
                                     keep_w(Q[d].w);
@@ -546,12 +548,14 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             if constexpr (WIDE && BSWP) {
                                 float4 Q[NDIR];
 #pragma unroll
-                                for (int d = d0; d < d1 && d < d0 + LB; ++d) {
+                                for (int d = 0; d < NDIR; ++d) {
+                                    if (d < d0 || d >= d1 || d >= d0 + LB) continue;
                                     Q[d] = xs[PAD - dir_off(d, N)];
                                     cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
                                 }
 #pragma unroll
-                                for (int d = d0; d < d1; ++d) {
+                                for (int d = 0; d < NDIR; ++d) {
+                                    if (d < d0 || d >= d1) continue;
                                     const int e = d + LB < d1 ? d + LB : d0;
                                     if (d + LB < d1) {
                                         Q[e] = xs[PAD - dir_off(e, N)];
