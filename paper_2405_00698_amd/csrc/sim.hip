@@ -834,8 +834,8 @@ struct PersistEntry {
 const PersistEntry kPersist[] = {
     SR_PLF(4, 128, 0, 3, 3, 1),  SR_PLF(5, 256, 0, 3, 3, 1),  SR_PLF(6, 384, 0, 3, 3, 1),  SR_PLF(7, 512, 0, 3, 3, 1),
     SR_PL(4, 128, 1, 0, 4),   SR_PL(5, 256, 1, 0, 4),   SR_PL(6, 384, 1, 0, 4),   SR_PL(7, 512, 1, 0, 4),
-    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLF(10, 448, 0, 3, 3, 1), SR_PVL(11, 256, 1, 2, 1, 1, 4),
-    SR_PLS(10, 512, 0, 12, 3),
+    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLS(10, 512, 0, 12, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PLF(10, 448, 0, 3, 3, 1),
     SR_PLB(8, 768, 0, 12, 4), SR_PLB(9, 1024, 0, 12, 8),
     SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
