@@ -174,15 +174,23 @@ int sr_persist_configs(int32_t n, int32_t *blocks, int32_t *variants, int32_t ca
 int pop_set_graphs(sr_pop *pop, int32_t enable);
 
 /* Picks the persistent kernel for robots of side n: block threads per
- * workgroup and variant (0 recompute every spring force at both ends,
- * 1 exchange spring coefficients through LDS, 2 exchange in two direction
- * chunks; +4 bounds the LDS loads in flight to save registers; +8 reads
- * positions with 12-byte instead of 16-byte LDS loads; +16 marks the kernels
- * with spring dashpots, which also share velocities through LDS: a population
- * with zeta_spring != 0 accepts only those, any other population only the
- * rest).  All variants of one kind give bit-identical results.
- * SR_EUNSUPPORTED for a combination the library lacks or that does not match
- * the population's physics. */
+ * workgroup and variant, a sum of
+ *   0 recompute every spring force at both ends, 1 exchange spring
+ *     coefficients through LDS, 2 exchange in two direction chunks;
+ *   +4 bounds the LDS loads in flight to save registers;
+ *   +8 reads positions with 12-byte instead of 16-byte LDS loads;
+ *   +16 marks the kernels with spring dashpots, which also share velocities
+ *     through LDS: a population with zeta_spring != 0 accepts only those, any
+ *     other population only the rest;
+ *   +32 / +64 rebuild the diagonal / all springs' parameters each step from
+ *     per-voxel terms (not after pop_set_spring_params); +128 keeps one
+ *     position buffer;
+ *   +256 * L keeps up to L + 1 neighbour reads in flight (L < 16);
+ *   +4096 * (B + 1) sets the backward springs' reads apart (B in flight);
+ *   +131072 / +262144 software-pipeline the backward / forward springs.
+ * sr_persist_configs lists the compiled combinations.  All variants of one
+ * kind give bit-identical results.  SR_EUNSUPPORTED for a combination the
+ * library lacks or that does not match the population's physics. */
 int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t variant);
 /* The persistent kernel configuration in use for side n (host outputs). */
 int pop_get_persist_variant(sr_pop *pop, int32_t n, int32_t *block, int32_t *variant);
