@@ -194,3 +194,27 @@ def test_genome_gradient_weighted_actuation(orc):
         assert e < 2e-2
         checked += 1
     assert checked >= 3
+
+
+@pytest.mark.parametrize("n", [4, 6, 8, 9, 10, 11, 12])
+def test_phase_kernels_bitwise_equal_per_step_kernel(n):
+    # weight-scaled actuation without dashpots: nonzero phases, so every
+    # compiled non-dashpot configuration runs its phase form
+    from paper_2405_00698_amd import api
+    sides = [n] * 3
+    cls, w = voxel_population(sides, 68)
+    over = dict(zeta_spring=0.0, zeta_ground=0.0)
+    ref = _pop(sides, cls, w, **over)
+    assert np.abs(ref.springs()["phi"].cpu().numpy()).max() > 0
+    ref.set_step_config(SR_STEP_PLAIN)
+    ref.step(150)
+    xr, vr, _ = ref.state()
+    configs = [(b, v) for b, v in api.persist_configs(n) if not v & 16]
+    assert configs
+    for b, v in configs:
+        say("phase kernel", n, b, v)
+        P = _pop(sides, cls, w, **over)
+        P.set_persist_variant(n, b, v)
+        P.step(150)
+        x, vv, _ = P.state()
+        assert torch.equal(x, xr) and torch.equal(vv, vr), (b, v)
