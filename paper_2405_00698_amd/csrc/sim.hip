@@ -238,8 +238,8 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
           int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
-    static_assert(!FSWP || (WIDE && VAR == 1 && !DASH && LAG > 0),
-                  "the software-pipelined forward springs are a form of the plain one-chunk exchange");
+    static_assert(!FSWP || (WIDE && VAR == 1 && LAG > 0),
+                  "the software-pipelined forward springs are a form of the one-chunk exchange");
     constexpr int LB = LAGB < 0 ? LAG : LAGB;
     static_assert(VOX == 0 || VAR != 0, "voxel-rebuilt parameters need an exchange variant");
     static_assert((LAG == 0 && LB == 0) || VAR == 1,
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
                             if constexpr (FSWP) {
-                                float4 Q[NDIR];
+                                float4 Q[NDIR], QV[DASH ? NDIR : 1];
                                 float4 Vx[VOX > 0 ? 8 : 1];
                                 if constexpr (VOX > 0) {
                                     // re-read every step (see below)
@@ -414,15 +414,22 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                 }
 #pragma unroll
                                 for (int d = 0; d < NDIR; ++d)
-                                    if (d >= d0 && d < d1 && d < d0 + LAG) Q[d] = xs[PAD + dir_off(d, N)];
+                                    if (d >= d0 && d < d1 && d < d0 + LAG) {
+                                        Q[d] = xs[PAD + dir_off(d, N)];
+                                        if constexpr (DASH) QV[DASH ? d : 0] = vb[s + PAD + dir_off(d, N)];
+                                    }
 #pragma unroll
                                 for (int d = 0; d < NDIR; ++d) {
                                     if (d < d0 || d >= d1) continue;
                                     const int e = d + LAG < d1 ? d + LAG : d0;
-                                    if (d + LAG < d1) Q[e] = xs[PAD + dir_off(e, N)];
+                                    if (d + LAG < d1) {
+                                        Q[e] = xs[PAD + dir_off(e, N)];
+                                        if constexpr (DASH) QV[DASH ? e : 0] = vb[s + PAD + dir_off(e, N)];
+                                    }
                                     keep_w(Q[d].w);
+                                    if constexpr (DASH) keep_w(QV[DASH ? d : 0].w);
                                     const float dx = Q[d].x - xr[k].x, dy = Q[d].y - xr[k].y, dz = Q[d].z - xr[k].z;
-                                    float kk, al, be;
+                                    float kk, al, be, cd;
                                     if (from_vox(VOX, d)) {
                                         float4 sm = Vx[VOX > 0 ? vox_idx(d, 0) : 0];
 #pragma unroll
@@ -431,17 +438,27 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                             sm.x = add_nf(sm.x, u.x);
                                             sm.y = add_nf(sm.y, u.y);
                                             if (PHASE) sm.z = add_nf(sm.z, u.z);
+                                            if (DASH) sm.w = add_nf(sm.w, u.w);
                                         }
                                         kk = sm.x;
                                         al = mul_nf(sm.y, L0d(c, d));
                                         be = PHASE ? mul_nf(sm.z, L0d(c, d)) : 0.f;
+                                        cd = sm.w;
                                     } else {
                                         kk = pk[k][d];
                                         al = pa[k][d];
                                         be = PHASE ? pb[k][d] : 0.f;
+                                        cd = DASH ? pd[k][DASH ? d : 0] : 0.f;
                                     }
-                                    const float cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y,
-                                                                        len2(dx, dy, dz));
+                                    float cf;
+                                    if constexpr (DASH) {
+                                        const float4 W = QV[DASH ? d : 0];
+                                        cf = spring_coef_d<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz),
+                                                                  cd,
+                                                                  rate(W.x - vr[k].x, W.y - vr[k].y, W.z - vr[k].z, dx, dy, dz));
+                                    } else {
+                                        cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz));
+                                    }
                                     cs[(d - d0) * CL + PAD] = cf;
                                     Ff[k].x = fmaf(cf, dx, Ff[k].x);
                                     Ff[k].y = fmaf(cf, dy, Ff[k].y);
@@ -819,6 +836,20 @@ struct PersistEntry {
         NN, BS, VAR + 16, k_persist<NN + 1, BS, VAR, false, true, false, true, true>,                   \
             k_persist<NN + 1, BS, VAR, false, true, false, true, true>, lds_bytes<NN + 1, BS, VAR, true>() \
     }
+#define SR_PDF(NN, BS, LF, LB)                                                                              \
+    {                                                                                                        \
+        NN, BS, 1 + 16 + 256 * LF + 4096 * (LB + 1) + 131072 + 262144,                                       \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB, true, true>,          \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB, true, true>,          \
+            lds_bytes<NN + 1, BS, 1, true>()                                                                 \
+    }
+#define SR_PDVF(NN, BS, VOX, SBX, LF, LB)                                                                   \
+    {                                                                                                        \
+        NN, BS, 1 + 16 + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1) + 131072 + 262144,                \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, VOX, SBX, LF, LB, true, true>,          \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, VOX, SBX, LF, LB, true, true>,          \
+            lds_bytes<NN + 1, BS, 1, true, VOX, SBX>()                                                       \
+    }
 #define SR_PDL(NN, BS, LF, LB)                                                                         \
     {                                                                                                    \
         NN, BS, 1 + 16 + 256 * LF + 4096 * (LB + 1),                                                     \
@@ -875,14 +906,17 @@ const PersistEntry kPersist[] = {
     SR_PLF(10, 512, 0, 6, 3, 1), SR_PLS(9, 1024, 0, 12, 4),   SR_PLF(8, 256, 0, 3, 3, 1),  SR_PLF(9, 512, 0, 3, 3, 1),
     SR_PVLF(11, 896, 2, 1, 1, 3, 3, 1), SR_PVLF(11, 256, 1, 1, 1, 3, 3, 1),
     // spring dashpots (Table II model)
+    SR_PDF(4, 128, 3, 3),   SR_PDF(5, 256, 3, 3),   SR_PDF(6, 384, 3, 3),   SR_PDF(7, 512, 3, 3),
+    SR_PDF(8, 768, 3, 3),   SR_PDF(9, 1024, 3, 3),  SR_PDVF(10, 704, 2, 1, 3, 3), SR_PD(9, 1024, 1),
     SR_PDL(4, 128, 4, 4),   SR_PDL(5, 256, 4, 4),   SR_PDL(6, 384, 4, 4),   SR_PDL(7, 512, 4, 4),
-    SR_PDL(8, 768, 4, 4),   SR_PD(9, 1024, 1),
+    SR_PDL(8, 768, 4, 4),
     SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
     SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
     SR_PD(7, 512, 0),   SR_PD(8, 768, 1),   SR_PD(8, 768, 0),    SR_PD(9, 512, 1),
     SR_PD(9, 512, 0),   SR_PD(10, 512, 1),  SR_PD(10, 448, 1),   SR_PD(10, 704, 1),  SR_PD(11, 512, 2),
     SR_PD(11, 576, 2),  SR_PD(11, 896, 2),  SR_PD(12, 512, 0),   SR_PD(12, 768, 0),
     SR_PDL(8, 768, 12, 0),  SR_PDL(5, 256, 12, 0),
+    SR_PDF(9, 512, 3, 3),   SR_PDVF(10, 512, 2, 1, 3, 3), SR_PDVF(10, 448, 2, 1, 3, 3), SR_PDVF(10, 512, 1, 1, 3, 3),
 };
 
 #define SR_REC(NN, BS, VAR) \
