@@ -1,7 +1,9 @@
 """Tuner for the persistent step kernel: for every grid side present in a
 population, times each compiled (workgroup size, exchange variant)
 configuration on the live population and keeps the fastest.  Results are
-cached in a JSON file keyed by (device name, side, population bucket)."""
+cached in a JSON file keyed by (device name, side, population bucket, spring
+model, the library's configuration list for that side)."""
+import hashlib
 import json
 import os
 import time
@@ -56,16 +58,21 @@ def tune(pop, steps=200, cache_path=None, verbose=False):
         counts[n] = counts.get(n, 0) + 1
     result = {}
     for n, cnt in sorted(counts.items()):
-        key = "%s|n=%d|R<=%d%s" % (dev_name, n, _bucket(cnt), "|dash" if pop.dashpots else "")
+        configs = api.persist_configs(n)
+        lib = hashlib.sha256(repr(configs).encode()).hexdigest()[:12]
+        key = "%s|n=%d|R<=%d%s|%s" % (dev_name, n, _bucket(cnt), "|dash" if pop.dashpots else "", lib)
         if key in cache:
             b, v, t = cache[key]
-            pop.set_persist_variant(n, b, v)
-            result[n] = (b, v, t)
-            continue
+            try:
+                pop.set_persist_variant(n, b, v)
+                result[n] = (b, v, t)
+                continue
+            except api.SoftRobotError:
+                pass  # not usable for this population (e.g. spring parameters set directly): time again
         target = pop if len(counts) == 1 else _sub_population(pop, n)
         default = target.persist_variant(n)
         times = []
-        for b, v in api.persist_configs(n):
+        for b, v in configs:
             if bool(v & 16) != pop.dashpots:
                 continue  # kernels for the other spring model
             try:
