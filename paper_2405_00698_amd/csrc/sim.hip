@@ -225,6 +225,19 @@ __device__ __forceinline__ float4 vox4(float4 v) { return v; }
 __device__ __forceinline__ void vox_store(float2 &d, float4 v) { d = make_float2(v.x, v.y); }
 __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 
+// Template parameters of the persistent step kernel:
+//   N      lattice points per side (grid side + 1), so stencil offsets are immediates
+//   BS     threads per workgroup; each thread owns ceil(N^3 / BS) lattice slots
+//   VAR    0 recompute, 1 exchange coefficients through LDS, 2 in two direction chunks
+//   FENCE  a scheduling barrier after each slot bounds the reads in flight
+//   PHASE  the actuation has per-spring phases (k L0 a sin(phi) plane)
+//   REC    recording form for the adjoint (writes x_n and v'_n every step)
+//   WIDE   16-byte position reads (12-byte otherwise)
+//   DASH   spring dashpots: velocities mirrored in LDS
+//   VOX    1 / 2: diagonal / all springs' parameters rebuilt from voxel terms
+//   SBX    one position buffer (one more barrier per step)
+//   LAG, LAGB, BSWP, FSWP  how the neighbour reads are pipelined (below)
+//
 // LAG (exchange variants, 16-byte reads): the neighbour reads of a slot are
 // issued back to back with at most LAG + 1 outstanding; the read LAG places
 // earlier is waited for by keeping its .w alive, the last LAG ones where their
