@@ -212,6 +212,37 @@ constexpr size_t lds_bytes() {
            (VOX ? sizeof(float4) * G::CL : 0);
 }
 
+// Direction geometry as plain arithmetic, for loops over a run-time (wave-
+// uniform) direction: the forward directions are the 3x3x3 neighbourhood
+// cells after the centre in (dz, dy, dx) order, cell f = d + 14.  Written with
+// selects on the components only, so no lookup table is built.
+__host__ __device__ constexpr int rdx(int d) { return (d + 14) % 3 - 1; }
+__host__ __device__ constexpr int rdy(int d) { return (d + 14) / 3 % 3 - 1; }
+__host__ __device__ constexpr int rdz(int d) { return (d + 14) / 9 - 1; }
+__host__ __device__ constexpr int rdir_off(int d, int N) { return rdx(d) + N * (rdy(d) + N * rdz(d)); }
+__host__ __device__ constexpr int rvox_cnt(int d) {
+    return (rdx(d) == 0 ? 2 : 1) * (rdy(d) == 0 ? 2 : 1) * (rdz(d) == 0 ? 2 : 1);
+}
+__host__ __device__ constexpr int rvox_idx(int d, int i) {
+    const int dx = rdx(d), dy = rdy(d), dz = rdz(d);
+    const int nx = dx == 0 ? 2 : 1, ny = dy == 0 ? 2 : 1;
+    const int ix = i % nx, iy = (i / nx) % ny, iz = i / (nx * ny);
+    const int ox = dx == 0 ? ix - 1 : (dx == 1 ? 0 : -1);
+    const int oy = dy == 0 ? iy - 1 : (dy == 1 ? 0 : -1);
+    const int oz = dz == 0 ? iz - 1 : 0;
+    return (ox + 1) + 2 * (oy + 1) + 4 * (oz + 1);
+}
+constexpr bool rdir_matches() {
+    for (int d = 0; d < NDIR; ++d) {
+        if (rdx(d) != dir_dx(d) || rdy(d) != dir_dy(d) || rdz(d) != dir_dz(d) || rvox_cnt(d) != vox_cnt(d))
+            return false;
+        for (int i = 0; i < vox_cnt(d); ++i)
+            if (rvox_idx(d, i) != vox_idx(d, i)) return false;
+    }
+    return true;
+}
+static_assert(rdir_matches(), "run-time direction geometry must equal the stencil table");
+
 template <bool WIDEV>
 struct VoxT {
     typedef float2 T;
@@ -237,6 +268,8 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 //   VOX    1 / 2: diagonal / all springs' parameters rebuilt from voxel terms
 //   SBX    one position buffer (one more barrier per step)
 //   LAG, LAGB, BSWP, FSWP  how the neighbour reads are pipelined (below)
+//   ROLL   direction loops left rolled, with no per-direction arrays: each
+//          iteration reads, computes and stores (offsets are wave-uniform)
 //
 // LAG (exchange variants, 16-byte reads): the neighbour reads of a slot are
 // issued back to back with at most LAG + 1 outstanding; the read LAG places
@@ -249,8 +282,11 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 // the same for the forward springs with window LAG (and stores each
 // coefficient as soon as it is computed).
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
-          int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false>
+          int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false,
+          bool ROLL = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    static_assert(!ROLL || (VAR >= 1 && VOX == 2 && !DASH && !REC && WIDE && LAG == 0 && !FSWP && !BSWP),
+                  "the rolled direction loop is a form of the exchange with every parameter from voxels");
     static_assert(!FSWP || (WIDE && VAR == 1 && LAG > 0),
                   "the software-pipelined forward springs are a form of the one-chunk exchange");
     constexpr int LB = LAGB < 0 ? LAG : LAGB;
@@ -401,6 +437,70 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             Fb[k].z = fmaf(cf, ez, Fb[k].z);
                         }
                     }
+                }
+            } else if constexpr (ROLL) {
+                // Rolled form: one direction per iteration and nothing indexed by
+                // it but LDS addresses, so no per-direction arrays go to scratch.
+                // The operations and their order are those of the unrolled form.
+                for (int ch = 0; ch < NCH; ++ch) {
+                    const int d0 = ch * NDC;
+                    const int d1 = (ch + 1) * NDC < NDIR ? (ch + 1) * NDC : NDIR;
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int s = tid + k * BS;
+                        if (s < SL) {
+                            const float4 *xs = xc + s;
+                            float *cs = coef + s;
+                            int vo = PAD + s;
+                            __asm__ volatile("" : "+v"(vo));
+#pragma unroll 1
+                            for (int d = d0; d < d1; ++d) {
+                                const float4 q = xs[PAD + rdir_off(d, N)];
+                                keep_w(q.w);
+                                const float dx = q.x - xr[k].x, dy = q.y - xr[k].y, dz = q.z - xr[k].z;
+                                float4 sm = vox4(vv[vo + vox_off(rvox_idx(d, 0), N)]);
+                                const int cnt = rvox_cnt(d);
+                                for (int i = 1; i < cnt; ++i) {
+                                    const float4 u = vox4(vv[vo + vox_off(rvox_idx(d, i), N)]);
+                                    sm.x = add_nf(sm.x, u.x);
+                                    sm.y = add_nf(sm.y, u.y);
+                                    if (PHASE) sm.z = add_nf(sm.z, u.z);
+                                }
+                                const int l2 = rdx(d) * rdx(d) + rdy(d) * rdy(d) + rdz(d) * rdz(d);
+                                const float L0 = l2 == 1 ? c.L0e : l2 == 2 ? c.L0f : c.L0b;
+                                const float kk = sm.x;
+                                const float cf = spring_coef<PHASE>(kk, kk * L0, mul_nf(sm.y, L0),
+                                                                    PHASE ? mul_nf(sm.z, L0) : 0.f, sct.x, sct.y,
+                                                                    len2(dx, dy, dz));
+                                cs[(d - d0) * CL + PAD] = cf;
+                                Ff[k].x = fmaf(cf, dx, Ff[k].x);
+                                Ff[k].y = fmaf(cf, dy, Ff[k].y);
+                                Ff[k].z = fmaf(cf, dz, Ff[k].z);
+                            }
+                        }
+                        if (FENCE) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int k = 0; k < NPT; ++k) {
+                        const int s = tid + k * BS;
+                        if (s < SL) {
+                            const float4 *xs = xc + s;
+                            const float *cs = coef + s;
+#pragma unroll 1
+                            for (int d = d0; d < d1; ++d) {
+                                const float4 q = xs[PAD - rdir_off(d, N)];
+                                const float cf = cs[(d - d0) * CL + (PAD - rdir_off(d, N))];
+                                keep_w(q.w);
+                                const float ex = q.x - xr[k].x, ey = q.y - xr[k].y, ez = q.z - xr[k].z;
+                                Fb[k].x = fmaf(cf, ex, Fb[k].x);
+                                Fb[k].y = fmaf(cf, ey, Fb[k].y);
+                                Fb[k].z = fmaf(cf, ez, Fb[k].z);
+                            }
+                        }
+                        if (FENCE) __builtin_amdgcn_sched_barrier(0);
+                    }
+                    if (ch + 1 < NCH) __syncthreads();
                 }
             } else {
 #pragma unroll
@@ -827,6 +927,14 @@ struct PersistEntry {
             k_persist<NN + 1, BS, 1, F, true, false, true, false, VOX, SBX, LF, LB, BSW, true>,              \
             lds_bytes<NN + 1, BS, 1, false, VOX, SBX>()                                                      \
     }
+// rolled direction loops (+2097152), every parameter from voxels
+#define SR_PR(NN, BS, VAR, SBX, F)                                                                           \
+    {                                                                                                        \
+        NN, BS, VAR + 4 * F + 64 + 128 * SBX + 2097152,                                                      \
+            k_persist<NN + 1, BS, VAR, F, false, false, true, false, 2, SBX, 0, -1, false, false, true>,     \
+            k_persist<NN + 1, BS, VAR, F, true, false, true, false, 2, SBX, 0, -1, false, false, true>,      \
+            lds_bytes<NN + 1, BS, VAR, false, 2, SBX>()                                                      \
+    }
 #define SR_PVLB(NN, BS, VOX, SBX, F, LF, LB)                                                              \
     {                                                                                                        \
         NN, BS, 1 + 4 * F + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1),                               \
@@ -881,7 +989,7 @@ const PersistEntry kPersist[] = {
     SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLS(10, 512, 0, 12, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4),
     SR_PLF(10, 448, 0, 3, 3, 1),
     SR_PLB(8, 768, 0, 12, 4), SR_PLB(9, 1024, 0, 12, 8),
-    SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
+    SR_PR(12, 1024, 2, 1, 1), SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
     SR_PE(6, 192, 1, 0, 1),   SR_PE(6, 384, 0, 0, 1),   SR_PE(7, 512, 1, 0, 1),   SR_PE(7, 256, 1, 0, 1),  SR_PE(7, 512, 0, 0, 1),
@@ -913,11 +1021,10 @@ const PersistEntry kPersist[] = {
     SR_PLB(9, 1024, 0, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 12, 4),
     SR_PVLB(11, 256, 2, 1, 1, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 4, 0),
     SR_PLB(7, 512, 0, 12, 0), SR_PLB(6, 384, 0, 12, 0), SR_PLB(5, 256, 0, 12, 0), SR_PLB(4, 128, 0, 12, 0),
-    SR_PLS(10, 512, 0, 12, 2), SR_PLS(10, 512, 0, 12, 4), SR_PLS(10, 448, 0, 12, 3), SR_PLS(8, 768, 0, 12, 4),
-    SR_PLS(10, 512, 0, 12, 1), SR_PLS(10, 448, 0, 12, 2), SR_PLB(10, 512, 0, 12, 0),
-    SR_PLF(10, 512, 0, 2, 2, 1), SR_PLF(10, 512, 0, 3, 3, 1), SR_PLF(10, 512, 0, 4, 2, 1),
-    SR_PLF(10, 512, 0, 6, 3, 1), SR_PLS(9, 1024, 0, 12, 4),   SR_PLF(8, 256, 0, 3, 3, 1),  SR_PLF(9, 512, 0, 3, 3, 1),
+    SR_PLS(8, 768, 0, 12, 4),  SR_PLB(10, 512, 0, 12, 0), SR_PLF(10, 512, 0, 3, 3, 1),
+    SR_PLS(9, 1024, 0, 12, 4), SR_PLF(8, 256, 0, 3, 3, 1),  SR_PLF(9, 512, 0, 3, 3, 1),
     SR_PVLF(11, 896, 2, 1, 1, 3, 3, 1), SR_PVLF(11, 256, 1, 1, 1, 3, 3, 1),
+    SR_PR(12, 768, 2, 1, 1),  SR_PR(12, 512, 2, 1, 1),
     // spring dashpots (Table II model)
     SR_PDF(4, 128, 3, 3),   SR_PDF(5, 256, 3, 3),   SR_PDF(6, 384, 3, 3),   SR_PDF(7, 512, 3, 3),
     SR_PDF(8, 768, 3, 3),   SR_PDF(9, 1024, 3, 3),  SR_PDVF(10, 704, 2, 1, 3, 3), SR_PD(9, 1024, 1),

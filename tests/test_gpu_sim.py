@@ -119,14 +119,13 @@ def test_plain_and_persistent_agree_bitwise():
                                              (448, 65), (704, 69), (256, 1), (256, 69), (256, 37), (448, 513), (448, 1025),
                                              (448, 1537), (512, 1025), (448, 1057), (512, 1057), (512, 1089), (448, 5121), (448, 4609),
                                              (448, 5633), (448, 6145), (448, 7169), (512, 5121), (512, 5633), (448, 5125),
-                                             (448, 15361), (512, 7169), (448, 7173), (512, 146433), (512, 154625),
-                                             (448, 150529), (512, 142337), (448, 146433), (512, 150529), (512, 406017),
-                                             (512, 410369), (512, 406529), (448, 410369), (512, 411137)]),
+                                             (448, 15361), (512, 7169), (448, 7173), (512, 150529), (512, 410369), (448, 410369)]),
                                        (11, [(256, 165), (896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
                                              (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221), (256, 23749), (256, 7365),
                                              (256, 5317), (256, 410533), (896, 410565)]),
                                        (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6), (768, 194), (768, 198),
-                                             (1024, 198), (576, 198), (256, 2), (256, 198)])])
+                                             (1024, 198), (576, 198), (256, 2), (256, 198), (1024, 2097350), (768, 2097350),
+                                             (512, 2097350)])])
 def test_persistent_variants_bitwise(n, configs):
     sides = [n] * 4
     cls, w = voxel_population(sides, 17)
