@@ -268,8 +268,9 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 //   VOX    1 / 2: diagonal / all springs' parameters rebuilt from voxel terms
 //   SBX    one position buffer (one more barrier per step)
 //   LAG, LAGB, BSWP, FSWP  how the neighbour reads are pipelined (below)
-//   ROLL   direction loops left rolled, with no per-direction arrays: each
-//          iteration reads, computes and stores (offsets are wave-uniform)
+//   ROLL   direction loops left rolled (1) or unrolled by two (2), with no
+//          per-direction arrays: each iteration reads, computes and stores
+//          (offsets are wave-uniform)
 //
 // LAG (exchange variants, 16-byte reads): the neighbour reads of a slot are
 // issued back to back with at most LAG + 1 outstanding; the read LAG places
@@ -283,9 +284,9 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 // coefficient as soon as it is computed).
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
           int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false,
-          bool ROLL = false>
+          int ROLL = 0>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
-    static_assert(!ROLL || (VAR >= 1 && VOX == 2 && !DASH && !REC && WIDE && LAG == 0 && !FSWP && !BSWP),
+    static_assert(ROLL == 0 || (VAR >= 1 && VOX == 2 && !DASH && !REC && WIDE && LAG == 0 && !FSWP && !BSWP),
                   "the rolled direction loop is a form of the exchange with every parameter from voxels");
     static_assert(!FSWP || (WIDE && VAR == 1 && LAG > 0),
                   "the software-pipelined forward springs are a form of the one-chunk exchange");
@@ -438,7 +439,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         }
                     }
                 }
-            } else if constexpr (ROLL) {
+            } else if constexpr (ROLL > 0) {
                 // Rolled form: one direction per iteration and nothing indexed by
                 // it but LDS addresses, so no per-direction arrays go to scratch.
                 // The operations and their order are those of the unrolled form.
@@ -453,7 +454,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             float *cs = coef + s;
                             int vo = PAD + s;
                             __asm__ volatile("" : "+v"(vo));
-#pragma unroll 1
+#pragma unroll ROLL
                             for (int d = d0; d < d1; ++d) {
                                 const float4 q = xs[PAD + rdir_off(d, N)];
                                 keep_w(q.w);
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         if (s < SL) {
                             const float4 *xs = xc + s;
                             const float *cs = coef + s;
-#pragma unroll 1
+#pragma unroll ROLL
                             for (int d = d0; d < d1; ++d) {
                                 const float4 q = xs[PAD - rdir_off(d, N)];
                                 const float cf = cs[(d - d0) * CL + (PAD - rdir_off(d, N))];
@@ -928,11 +929,13 @@ struct PersistEntry {
             lds_bytes<NN + 1, BS, 1, false, VOX, SBX>()                                                      \
     }
 // rolled direction loops (+2097152), every parameter from voxels
-#define SR_PR(NN, BS, VAR, SBX, F)                                                                           \
+#define SR_PR(NN, BS, VAR, SBX, F) SR_PRU(NN, BS, VAR, SBX, F, 1)
+// unrolled by two: + 4194304
+#define SR_PRU(NN, BS, VAR, SBX, F, U)                                                                       \
     {                                                                                                        \
-        NN, BS, VAR + 4 * F + 64 + 128 * SBX + 2097152,                                                      \
-            k_persist<NN + 1, BS, VAR, F, false, false, true, false, 2, SBX, 0, -1, false, false, true>,     \
-            k_persist<NN + 1, BS, VAR, F, true, false, true, false, 2, SBX, 0, -1, false, false, true>,      \
+        NN, BS, VAR + 4 * F + 64 + 128 * SBX + 2097152 + 4194304 * (U - 1),                                  \
+            k_persist<NN + 1, BS, VAR, F, false, false, true, false, 2, SBX, 0, -1, false, false, U>,        \
+            k_persist<NN + 1, BS, VAR, F, true, false, true, false, 2, SBX, 0, -1, false, false, U>,         \
             lds_bytes<NN + 1, BS, VAR, false, 2, SBX>()                                                      \
     }
 #define SR_PVLB(NN, BS, VOX, SBX, F, LF, LB)                                                              \
@@ -986,10 +989,12 @@ struct PersistEntry {
 const PersistEntry kPersist[] = {
     SR_PLF(4, 128, 0, 3, 3, 1),  SR_PLF(5, 256, 0, 3, 3, 1),  SR_PLF(6, 384, 0, 3, 3, 1),  SR_PLF(7, 512, 0, 3, 3, 1),
     SR_PL(4, 128, 1, 0, 4),   SR_PL(5, 256, 1, 0, 4),   SR_PL(6, 384, 1, 0, 4),   SR_PL(7, 512, 1, 0, 4),
-    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLS(10, 512, 0, 12, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLS(10, 512, 0, 12, 3), SR_PRU(11, 896, 1, 1, 1, 3),
+    SR_PVL(11, 256, 1, 2, 1, 1, 4),
     SR_PLF(10, 448, 0, 3, 3, 1),
     SR_PLB(8, 768, 0, 12, 4), SR_PLB(9, 1024, 0, 12, 8),
-    SR_PR(12, 1024, 2, 1, 1), SR_PV(12, 768, 2, 2, 1, 1),  SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
+    SR_PRU(12, 768, 2, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 2), SR_PR(12, 1024, 2, 1, 1), SR_PV(12, 768, 2, 2, 1, 1),
+    SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
     SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
     SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
     SR_PE(6, 192, 1, 0, 1),   SR_PE(6, 384, 0, 0, 1),   SR_PE(7, 512, 1, 0, 1),   SR_PE(7, 256, 1, 0, 1),  SR_PE(7, 512, 0, 0, 1),
@@ -1024,7 +1029,9 @@ const PersistEntry kPersist[] = {
     SR_PLS(8, 768, 0, 12, 4),  SR_PLB(10, 512, 0, 12, 0), SR_PLF(10, 512, 0, 3, 3, 1),
     SR_PLS(9, 1024, 0, 12, 4), SR_PLF(8, 256, 0, 3, 3, 1),  SR_PLF(9, 512, 0, 3, 3, 1),
     SR_PVLF(11, 896, 2, 1, 1, 3, 3, 1), SR_PVLF(11, 256, 1, 1, 1, 3, 3, 1),
-    SR_PR(12, 768, 2, 1, 1),  SR_PR(12, 512, 2, 1, 1),
+    SR_PR(12, 768, 2, 1, 1),  SR_PRU(12, 1024, 2, 1, 1, 2), SR_PRU(12, 512, 2, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 5),
+    SR_PRU(12, 768, 2, 1, 1, 7), SR_PRU(12, 768, 2, 1, 0, 3), SR_PRU(11, 576, 1, 1, 1, 3),
+    SR_PRU(11, 512, 1, 1, 1, 4), SR_PRU(11, 896, 1, 1, 1, 4),
     // spring dashpots (Table II model)
     SR_PDF(4, 128, 3, 3),   SR_PDF(5, 256, 3, 3),   SR_PDF(6, 384, 3, 3),   SR_PDF(7, 512, 3, 3),
     SR_PDF(8, 768, 3, 3),   SR_PDF(9, 1024, 3, 3),  SR_PDVF(10, 704, 2, 1, 3, 3), SR_PD(9, 1024, 1),

@@ -122,10 +122,12 @@ def test_plain_and_persistent_agree_bitwise():
                                              (448, 15361), (512, 7169), (448, 7173), (512, 150529), (512, 410369), (448, 410369)]),
                                        (11, [(256, 165), (896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
                                              (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221), (256, 23749), (256, 7365),
-                                             (256, 5317), (256, 410533), (896, 410565)]),
+                                             (256, 5317), (256, 410533), (896, 410565), (896, 10485957), (576, 10485957),
+                                             (512, 14680261), (896, 14680261)]),
                                        (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6), (768, 194), (768, 198),
                                              (1024, 198), (576, 198), (256, 2), (256, 198), (1024, 2097350), (768, 2097350),
-                                             (512, 2097350)])])
+                                             (1024, 6291654), (768, 6291654), (768, 10485958), (512, 10485958), (768, 18874566),
+                                             (768, 27263174), (768, 10485954)])])
 def test_persistent_variants_bitwise(n, configs):
     sides = [n] * 4
     cls, w = voxel_population(sides, 17)
