@@ -7,12 +7,19 @@ mesh build, 10,000 simulation steps in the persistent LDS-resident kernel,
 fitness, and the GA generation that produces the next genomes.  The metric is
 spring updates per second over the whole generation.
 
-Prints one JSON line (rank 0).  Only one GPU is supported: the population
-would shard across GPUs by robots, which this benchmark does not run.
+Beside it the line carries the step kernel's LDS roofline (the bound the
+metric names) and its VALU roofline, the other workloads of the method
+(256 robots of 8^3; the uneven 1024-robot population over 20 generations;
+the adjoint/forward time ratio at 64 robots of 8^3), the per-step-launch
+form on the same GPU, and the FP64 oracle timed on the host cores.
+
+Prints one JSON line.  Only one GPU is supported: the population would shard
+across GPUs by robots, which this benchmark does not run.
 """
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -21,22 +28,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# roofline denominators (MI355X: 256 CUs at 2.4 GHz)
+# Roofline denominators (MI355X: 256 CUs at 2.4 GHz).
 CU, CLK = 256, 2.4e9
-LDS_PEAK_GBS = CU * 128 * CLK / 1e9          # 128 B/clk/CU LDS bandwidth
-VALU_PEAK_SLOTS = CU * 64 * CLK               # FP32 lane-op issue slots/s without packed math
-LDS_B_PER_SPRING = 24.0                      # both endpoint positions, FP32 xyz
-LDS_B_PER_MASS = 12.0                        # each mass publishes its position
-VALU_SLOTS_PER_SPRING = 18.0                 # one force evaluation applied to both ends
-VALU_SLOTS_PER_MASS = 20.0                   # gravity, ground, friction, damping, integrate
+# LDS: CDNA4 reads 256 B/clk/CU with ds_read_b128 (twice CDNA3's 128 B/clk)
+LDS_PEAK_GBS = CU * 256 * CLK / 1e9
+# VALU: 4 SIMDs x 16 lanes per CU issue one FP32 lane-op slot per clock each;
+# packed FP32 is not used by this library, so this unpacked rate is the ceiling
+VALU_PEAK_SLOTS = CU * 64 * CLK
+# Algorithmic work per unit (one spring update = one spring force applied to
+# both ends in one step; one mass update = one node integrated in one step):
+LDS_B_PER_SPRING = 24.0      # both endpoint positions, FP32 xyz
+LDS_B_PER_MASS = 12.0        # each mass publishes its new position
+# 3 sub (d), 3 (r^2), v_rsq_f32 (4 slots), 1 (r), 2 fma (actuated L), 1 sub,
+# 2 mul (f / r), 3 mul (F), 3 add (both ends' accumulators)
+VALU_SLOTS_PER_SPRING = 22.0
+# gravity, ground normal, friction, damping, semi-implicit Euler
+VALU_SLOTS_PER_MASS = 25.0
 
 
-def measured_traffic(kernel_cfg, sim_steps, key="hbm_bytes_per_launch"):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE passes (scaled by a copy probe), or with
-    key="lds_bytes_per_launch" the LDS bytes its instructions moved (LDS
-    bandwidth counters); None when the kernel source or the launch differs from
-    the one measured."""
+def measured_counters(kernel_cfg, sim_steps, key):
+    """A per-launch counter figure of the step kernel from the committed
+    rocprofv3 summary (profiles/hbm_traffic.json): key "hbm_bytes_per_launch"
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy probe) or "lds_bytes_per_launch"
+    (LDS bandwidth counters); None when the kernel source or the launch differs
+    from the one measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
@@ -64,10 +79,12 @@ def parse():
     ap.add_argument("--mode", default="persistent", choices=["persistent", "plain"])
     ap.add_argument("--query", default="fp32", choices=["bf16", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=5000)
     ap.add_argument("--cpu-robots", type=int, default=64)
+    ap.add_argument("--cpu-steps", type=int, default=10000)
+    ap.add_argument("--cpu-single-robots", type=int, default=8)
+    ap.add_argument("--cpu-single-steps", type=int, default=2500)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the per-step-launch baseline and the adjoint/forward ratio")
+                    help="skip the other workloads, the per-step-launch form and the adjoint ratio")
     ap.add_argument("--no-tune", action="store_true", help="keep the default step-kernel configuration")
     ap.add_argument("--kernel", default=None,
                     help="BLOCK,VARIANT: run the uniform workload with this step-kernel configuration (no tuning)")
@@ -76,21 +93,63 @@ def parse():
     return ap.parse_args()
 
 
+def host_cpu():
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    return model
+
+
 def cpu_baseline(args, genomes, B):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload."""
+    """The FP64 oracle (built -O3 -march=native on this host) on the host
+    cores, on bounded samples of the workload: all threads over robots, and
+    one thread."""
     import oracle
-    from paper_2405_00698_amd import inputs  # noqa: F401
-    oracle.build()
-    robots = [oracle.robot_from_genome(genomes[r].astype(np.float64), B.astype(np.float64), args.side)
-              for r in range(args.cpu_robots)]
-    S = sum(R.S for R in robots)
-    t = time.perf_counter()
-    oracle.pop_step(robots, args.cpu_steps)
-    dt = time.perf_counter() - t
-    return {"value": S * args.cpu_steps / dt, "unit": "spring updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d robots of %d^3 from the same genomes, %d steps, FP64, one robot per thread (%.1f s)"
-                      % (args.cpu_robots, args.side, args.cpu_steps, dt)}
+    oracle.use_native()
+    threads = oracle.num_threads()
+    out = {"unit": "spring updates/s", "kind": "oracle", "cpu_model": host_cpu(), "nproc": os.cpu_count()}
+    for label, nr, steps, th in (("all", args.cpu_robots, args.cpu_steps, threads),
+                                 ("single", args.cpu_single_robots, args.cpu_single_steps, 1)):
+        oracle.set_threads(th)
+        robots = [oracle.robot_from_genome(genomes[r].astype(np.float64), B.astype(np.float64), args.side)
+                  for r in range(nr)]
+        S = sum(R.S for R in robots)
+        t = time.perf_counter()
+        oracle.pop_step(robots, steps)
+        dt = time.perf_counter() - t
+        rate = S * steps / dt
+        if label == "all":
+            out.update(value=rate, cores=th,
+                       sample="%d robots of %d^3 from the same genomes, %d steps, FP64, one robot per thread "
+                              "(%.1f s)" % (nr, args.side, steps, dt))
+        else:
+            out.update(single_thread_value=rate,
+                       single_thread_sample="%d robots of %d^3, %d steps, one thread (%.1f s)"
+                                            % (nr, args.side, steps, dt))
+        del robots
+    oracle.set_threads(threads)
+    return out
+
+
+def timed_steps(P, torch, steps):
+    """Seconds of one pop_step(steps) from HIP events on the population's stream."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(P.stream)
+    P.step(steps)
+    e1.record(P.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3
 
 
 def plain_baseline(api, inputs, torch, R, n, steps, prec):
@@ -104,15 +163,74 @@ def plain_baseline(api, inputs, torch, R, n, steps, prec):
     S = sum(P.counts()[1])
     P.step(20)
     torch.cuda.synchronize()
-    t = time.perf_counter()
-    P.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t
+    dt = timed_steps(P, torch, steps)
     P.close()
     return S * steps / dt
 
 
-def model_rates(api, inputs, torch, R, n, steps, prec):
+def uniform_workload(api, inputs, torch, R, n, steps, prec, tune_cache):
+    """R robots of n^3 from random genomes: tuned persistent step rate."""
+    from paper_2405_00698_amd import tune
+    dev = torch.device("cuda:0")
+    P = api.Population([n] * R)
+    P.build_from_genomes(torch.from_numpy(inputs.random_genomes(R)).to(dev),
+                         torch.from_numpy(inputs.gaussian_B()).to(dev), prec)
+    tuned = tune.tune(P, steps=min(steps, 500), cache_path=tune_cache)
+    S = sum(P.counts()[1])
+    P.step(20)
+    P.reset()
+    dt = timed_steps(P, torch, steps)
+    out = {"workload": "%d robots on %d^3 grids, %d steps" % (R, n, steps), "springs": S,
+           "spring_updates_per_s": S * steps / dt, "seconds": dt, "kernel": P.kernel_config(n),
+           "tuned": {str(k): list(v) for k, v in tuned.items()}}
+    P.close()
+    return out
+
+
+def uneven_generations(api, inputs, torch, R, gens, steps, tune_cache):
+    """The uneven population as configured: R robots with sides uniform on
+    4..12 and empty fractions spread 0.1..0.5, BF16-MFMA genome query, `gens`
+    generations of (build -> steps -> fitness -> GA, Table I rates)."""
+    from paper_2405_00698_amd import SR_QUERY_BF16, tune
+    from paper_2405_00698_amd.api import GAConfig, ga_generation
+    dev = torch.device("cuda:0")
+    sides = [int(q) for q in inputs.grid_sides(R, 4, 12)]
+    G = [torch.from_numpy(inputs.random_genomes(R, empty_bias=inputs.uniform(R, -0.2, 0.4, seed=2))).to(dev),
+         torch.empty((R, 8710), dtype=torch.float32, device=dev)]
+    B = torch.from_numpy(inputs.gaussian_B()).to(dev)
+    fit = torch.empty(R, dtype=torch.float32, device=dev)
+    P = api.Population(sides)
+    P.build_from_genomes(G[0], B, SR_QUERY_BF16)
+    tuned = tune.tune(P, steps=500, cache_path=tune_cache)
+    cfg = GAConfig()
+    springs, sim_s = 0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(gens):
+        P.build_from_genomes(G[g % 2], B, SR_QUERY_BF16)
+        springs += sum(P.counts()[1])
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(P.stream)
+        P.step(steps)
+        e1.record(P.stream)
+        P.fitness(fit)
+        ga_generation(fit, G[g % 2], G[(g + 1) % 2], cfg, seed=inputs.SEED_GA, generation=g)
+        e1.synchronize()
+        sim_s += e0.elapsed_time(e1) / 1e3
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"workload": "%d robots with sides uniform on 4..12, empty fractions 0.1..0.5, BF16-MFMA query, "
+                       "%d generations of %d steps, GA on (Table I rates)" % (R, gens, steps),
+           "spring_updates_per_s": springs * steps / wall, "sim_spring_updates_per_s": springs * steps / sim_s,
+           "seconds": wall, "sim_seconds": sim_s, "generations": gens,
+           "kernels": {str(q): P.kernel_config(q) for q in sorted(set(sides))},
+           "tuned": {str(k): list(v) for k, v in tuned.items()}}
+    P.close()
+    return out
+
+
+def model_rates(api, inputs, torch, R, n, steps, prec, tune_cache):
     """Step-kernel throughput of the base model and of the Table II model
     (weight-scaled muscles, spring and ground dashpots, static/kinetic
     friction) on the same genomes, each with its tuned kernel."""
@@ -124,46 +242,53 @@ def model_rates(api, inputs, torch, R, n, steps, prec):
     for name, params in (("base", _lib.default_params()), ("table2", _lib.table2_params())):
         P = api.Population([n] * R, params=params)
         P.build_from_genomes(G, B, prec)
-        cfg = tune.tune(P, steps=200, cache_path="/tmp/softrobot_tune.json")
+        tune.tune(P, steps=200, cache_path=tune_cache)
         S = sum(P.counts()[1])
         P.step(20)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        P.step(steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        out[name] = {"spring_updates_per_s": S * steps / dt, "kernel": P.kernel_config(n),
-                     "tuned_s": cfg[n][2]}
+        P.reset()
+        dt = timed_steps(P, torch, steps)
+        out[name] = {"spring_updates_per_s": S * steps / dt, "kernel": P.kernel_config(n)}
         P.close()
     return out
 
 
 def adjoint_ratio(api, inputs, torch):
     """64 robots of 8^3, 2000 steps, checkpoint every 100 steps: pop_backward
-    (segment recompute included) over the forward pop_step(2000)."""
+    (segment recompute included) over the forward pop_step(2000), the forward
+    timed both as it runs under recording (checkpoint copies between segment
+    launches) and as the production forward (one captured graph launch)."""
     from paper_2405_00698_amd import SR_QUERY_FP32
     dev = torch.device("cuda:0")
+    G = torch.from_numpy(inputs.random_genomes(64)).to(dev)
+    B = torch.from_numpy(inputs.gaussian_B()).to(dev)
+    F = api.Population([8] * 64)
+    F.build_from_genomes(G, B, SR_QUERY_FP32)
+    F.step(2000)
+    tg = []
+    for _ in range(5):
+        F.reset()
+        tg.append(timed_steps(F, torch, 2000))
+    F.close()
     P = api.Population([8] * 64)
-    P.build_from_genomes(torch.from_numpy(inputs.random_genomes(64)).to(dev),
-                         torch.from_numpy(inputs.gaussian_B()).to(dev), SR_QUERY_FP32)
+    P.build_from_genomes(G, B, SR_QUERY_FP32)
     P.record(100, 2000)
     dJ = torch.ones(64, device=dev)
     tf, tb = [], []
-    for _ in range(3):
+    for _ in range(5):
         P.reset()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        P.step(2000)
-        torch.cuda.synchronize()
-        tf.append(time.perf_counter() - t)
-        t = time.perf_counter()
+        tf.append(timed_steps(P, torch, 2000))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(P.stream)
         P.backward(dJ)
-        torch.cuda.synchronize()
-        tb.append(time.perf_counter() - t)
+        e1.record(P.stream)
+        e1.synchronize()
+        tb.append(e0.elapsed_time(e1) / 1e3)
     P.close()
-    f, b = float(np.median(tf)), float(np.median(tb))
-    return {"value": b / f, "forward_s": f, "backward_s": b,
-            "workload": "64 robots of 8^3, 2000 steps, checkpoint every 100, FP32"}
+    f, g, b = float(np.median(tf)), float(np.median(tg)), float(np.median(tb))
+    return {"value": b / g, "vs_recording_forward": b / f, "forward_graph_s": g, "forward_recording_s": f,
+            "backward_s": b, "workload": "64 robots of 8^3, 2000 steps, checkpoint every 100, FP32; "
+                                         "value = backward / forward as one graph launch"}
 
 
 def main():
@@ -175,9 +300,11 @@ def main():
     import torch
     from paper_2405_00698_amd import inputs, api, _lib
     from paper_2405_00698_amd import SR_QUERY_BF16, SR_QUERY_FP32, SR_STEP_PLAIN, SR_STEP_AUTO
+    from paper_2405_00698_amd.api import ga_generation, GAConfig
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    tune_cache = "/tmp/softrobot_tune.json"
     R, n = args.robots, args.side
     B = inputs.gaussian_B()
     if args.workload == "uneven":
@@ -192,28 +319,24 @@ def main():
     P = api.Population(sides)
     P.set_step_config(SR_STEP_PLAIN if args.mode == "plain" else SR_STEP_AUTO)
     prec = SR_QUERY_BF16 if args.query == "bf16" else SR_QUERY_FP32
-    has_ga = hasattr(_lib.load(), "ga_generation")
-    if has_ga:
-        from paper_2405_00698_amd.api import ga_generation, GAConfig
-        gacfg = GAConfig()
+    gacfg = GAConfig()
 
     tuned = None
     if args.kernel:
         b, v = (int(q) for q in args.kernel.split(","))
         P.set_persist_variant(args.side, b, v)
-    elif not args.no_tune:
+    elif not args.no_tune and args.mode == "persistent":
         # pick the fastest compiled step-kernel configuration for this population (cached)
         from paper_2405_00698_amd import tune
         P.build_from_genomes(Gt[0], Bt, prec)
-        tuned = {int(k): list(v) for k, v in tune.tune(P, steps=500, cache_path="/tmp/softrobot_tune.json").items()}
+        tuned = {int(k): list(v) for k, v in tune.tune(P, steps=500, cache_path=tune_cache).items()}
 
-    stream = torch.cuda.current_stream()
+    stream = P.stream
     springs_per_gen = []
     sim_ms = []
 
     def one_generation(g, record):
-        # without the GA the same genomes are rebuilt every generation
-        cur = Gt[g % 2] if has_ga else Gt[0]
+        cur = Gt[g % 2]
         P.build_from_genomes(cur, Bt, prec)
         M, S, _, _ = P.counts()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -222,8 +345,7 @@ def main():
         P.step(args.sim_steps)
         e1.record(stream)
         P.fitness(fit)
-        if has_ga:
-            ga_generation(fit, cur, Gt[(g + 1) % 2], gacfg, seed=inputs.SEED_GA, generation=g)
+        ga_generation(fit, cur, Gt[(g + 1) % 2], gacfg, seed=inputs.SEED_GA, generation=g)
         if record:
             springs_per_gen.append((sum(S), sum(M)))
             sim_ms.append((e0, e1))
@@ -240,16 +362,18 @@ def main():
     total_springs = sum(s for s, _ in springs_per_gen) * args.sim_steps
     total_masses = sum(m for _, m in springs_per_gen) * args.sim_steps
     value = total_springs / wall
+    # the step kernel's average launch time, from HIP events on the stream it runs on
     kern_s = sum(a.elapsed_time(b) for a, b in sim_ms) / 1e3 / len(sim_ms)
     su_per_launch = total_springs / len(sim_ms)
     mu_per_launch = total_masses / len(sim_ms)
-    lds_bytes = su_per_launch * LDS_B_PER_SPRING + mu_per_launch * LDS_B_PER_MASS
-    lds_gbs = lds_bytes / kern_s / 1e9
-    valu = (su_per_launch * VALU_SLOTS_PER_SPRING + mu_per_launch * VALU_SLOTS_PER_MASS) / kern_s
-    # LDS bytes the kernel's instructions actually moved per launch (counters),
-    # against the algorithmic bytes above
-    lds_traffic = (measured_traffic(P.kernel_config(n), args.sim_steps, "lds_bytes_per_launch")
-                   if args.mode == "persistent" and args.workload == "uniform" else None)
+    lds_alg = su_per_launch * LDS_B_PER_SPRING + mu_per_launch * LDS_B_PER_MASS
+    lds_gbs = lds_alg / kern_s / 1e9
+    valu_alg = su_per_launch * VALU_SLOTS_PER_SPRING + mu_per_launch * VALU_SLOTS_PER_MASS
+    valu = valu_alg / kern_s
+    counted = args.mode == "persistent" and args.workload == "uniform"
+    cfg_name = P.kernel_config(n) if counted else None
+    lds_moved = measured_counters(cfg_name, args.sim_steps, "lds_bytes_per_launch") if counted else None
+    hbm_moved = measured_counters(cfg_name, args.sim_steps, "hbm_bytes_per_launch") if counted else None
     out = {
         "metric": "spring updates/sec at 1 GPU (% LDS roofline); adjoint/forward time ratio",
         "value": value,
@@ -265,25 +389,28 @@ def main():
         "data": "synthetic: seeded random genomes (W ~ N(0, 1/64), b = 0), B ~ N(0, 1)",
         "config": {"workload": ("%d robots on %d^3 voxel grids" % (R, n) if args.workload == "uniform" else
                                 "%d robots with sides uniform on 4..12" % R) +
-                               ", %d sim steps per generation (dt 1e-4 s), %s genome query, GA %s"
-                               % (args.sim_steps, args.query, "on" if has_ga else "off"),
-                   "robots": R, "grid_side": n if args.workload == "uniform" else "4..12", "sim_steps": args.sim_steps, "mode": args.mode,
+                               ", %d sim steps per generation (dt 1e-4 s), %s genome query, GA on"
+                               % (args.sim_steps, args.query),
+                   "robots": R, "grid_side": n if args.workload == "uniform" else "4..12",
+                   "sim_steps": args.sim_steps, "mode": args.mode,
                    "springs_per_generation": springs_per_gen[0][0], "masses_per_generation": springs_per_gen[0][1],
                    "step_kernel": {q: P.kernel_config(q) for q in sorted(set(sides))}, "tuned": tuned},
         "sim_kernel_s": kern_s,
         "sim_spring_updates_per_s": su_per_launch / kern_s,
-        # The VALU floor (algorithmic lane-op slots at the unpacked issue rate) is
-        # higher than the LDS floor (algorithmic bytes at 128 B/clk/CU), so the
-        # arithmetic roofline is the one that bounds the step kernel.
-        "roofline": {"bound": "alu", "achieved": valu / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
-                     "unit": "T lane-op slots/s", "frac": valu / VALU_PEAK_SLOTS,
-                     "traffic": measured_traffic(P.kernel_config(n), args.sim_steps)
-                     if args.mode == "persistent" and args.workload == "uniform" else None},
-        "roofline_lds": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
-                         "frac": lds_gbs / LDS_PEAK_GBS, "traffic": lds_traffic,
-                         "traffic_frac": None if lds_traffic is None else lds_traffic / kern_s / 1e9 / LDS_PEAK_GBS},
-        "floors_s": {"alu": (su_per_launch * VALU_SLOTS_PER_SPRING + mu_per_launch * VALU_SLOTS_PER_MASS)
-                     / VALU_PEAK_SLOTS, "lds": lds_bytes / (LDS_PEAK_GBS * 1e9)},
+        # LDS bound: algorithmic bytes (24 B per spring update + 12 B per mass
+        # update) per launch over the launch time; traffic = the LDS bytes the
+        # kernel's instructions actually moved per launch (rocprofv3 counters)
+        "roofline": {"bound": "lds", "achieved": lds_gbs, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                     "frac": lds_gbs / LDS_PEAK_GBS, "traffic": lds_moved,
+                     "traffic_unit": "LDS bytes per launch (SQ_INSTS_LDS_LOAD/STORE_BANDWIDTH)",
+                     "algorithmic_bytes_per_launch": lds_alg},
+        # VALU co-bound: algorithmic FP32 lane-op slots (22 per spring update,
+        # 25 per mass update) over the launch time, against the unpacked issue rate
+        "roofline_valu": {"bound": "alu", "achieved": valu / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                          "unit": "T lane-op slots/s", "frac": valu / VALU_PEAK_SLOTS,
+                          "algorithmic_slots_per_launch": valu_alg},
+        "hbm_traffic_per_launch": hbm_moved,
+        "floors_s": {"lds": lds_alg / (LDS_PEAK_GBS * 1e9), "alu": valu_alg / VALU_PEAK_SLOTS},
     }
     if args.copy_probe:
         src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -296,15 +423,21 @@ def main():
                                                          "valu_fma", "valu_rsq")}
         out["measured_peaks"] = {k: (v / 1e9 if k.startswith("lds") else v / 1e12) for k, v in peaks.items()}
         out["measured_peaks"]["units"] = "LDS GB/s, VALU T lane-ops/s"
-        out["roofline_lds"]["frac_of_measured_lds_16B"] = lds_gbs / out["measured_peaks"]["lds_read_16B"]
-        out["roofline"]["frac_of_measured_fma"] = valu / peaks["valu_fma"]
+        out["roofline"]["frac_of_measured_lds_16B"] = lds_gbs / out["measured_peaks"]["lds_read_16B"]
+        if lds_moved is not None:
+            out["roofline"]["moved_over_algorithmic"] = lds_moved / lds_alg
+        out["roofline_valu"]["frac_of_measured_fma"] = valu / peaks["valu_fma"]
         P.close()
         pl = plain_baseline(api, inputs, torch, R, n, 500, prec)
         out["per_step_launch_spring_updates_per_s"] = pl
         out["persistent_over_per_step_launch"] = (su_per_launch / kern_s) / pl
         out["adjoint_forward_ratio"] = adjoint_ratio(api, inputs, torch)
-        out["material_models"] = [model_rates(api, inputs, torch, 4096, 5, 10000, prec),
-                                  model_rates(api, inputs, torch, 1024, 8, 5000, prec)]
+        out["workloads"] = {
+            "c2_256x8cubed": uniform_workload(api, inputs, torch, 256, 8, 10000, prec, tune_cache),
+            "c3_uneven_1024": uneven_generations(api, inputs, torch, 1024, 20, 10000, tune_cache),
+            "table2_model": [model_rates(api, inputs, torch, 4096, 5, 10000, prec, tune_cache),
+                             model_rates(api, inputs, torch, 1024, 8, 5000, prec, tune_cache)],
+        }
     if not args.no_cpu_baseline and args.workload == "uniform":
         out["cpu_baseline"] = cpu_baseline(args, G, B)
     print(json.dumps(out), flush=True)

@@ -195,7 +195,11 @@ int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t varia
 /* The persistent kernel configuration in use for side n (host outputs). */
 int pop_get_persist_variant(sr_pop *pop, int32_t n, int32_t *block, int32_t *variant);
 
-/* Advances every robot n_steps >= 0 steps.  Step n -> n+1 (t_n = n dt):
+/* Time stepping of the spring-mass robots (Sec. II-C: every robot's springs
+ * and masses advanced in parallel; physics per Table II: rest length, mass per
+ * node, stiffness per material, muscle actuation, gravity, ground elasticity
+ * and friction).
+ * Advances every robot n_steps >= 0 steps.  Step n -> n+1 (t_n = n dt):
  * spring forces k (r - L(t_n)) along each spring with L = L0 (1 + a sin(2 pi f
  * t_n + phi)) plus, with zeta_spring, the dashpot c (v_j - v_i).d^; gravity
  * -m g e_z; ground normal N = k_ground max(0, -z) (minus the contact damper

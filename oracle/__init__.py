@@ -22,18 +22,42 @@ GENOME_LEN = 8710
 NO_GRAVITY, NO_GROUND, NO_ACTUATION, WEIGHT_ACTUATION = 1, 2, 4, 8
 
 
+LIB_NATIVE = os.path.join(HERE, "liboracle_native.so")
+# no -ffast-math anywhere: the oracle keeps IEEE FP64 semantics
+_FLAGS = ["-std=gnu11", "-fPIC", "-shared", "-fopenmp"]
+
+
 def build(force=False):
-    """Compile liboracle.so with gcc (plain -O2, no fast-math, OpenMP over robots)."""
+    """Compile liboracle.so with gcc (-O3 for any x86-64 host, no fast-math,
+    OpenMP over robots).  The tests load this build."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
-                           SRC, "-o", tmp, "-lm"])
+    subprocess.check_call(["gcc", "-O3"] + _FLAGS + [SRC, "-o", tmp, "-lm"])
     os.replace(tmp, LIB)
     return LIB
 
 
+def build_native():
+    """Compile liboracle_native.so with -O3 -march=native for the host that
+    runs it (always rebuilt: the library must match this machine's CPU)."""
+    tmp = LIB_NATIVE + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O3", "-march=native"] + _FLAGS + [SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, LIB_NATIVE)
+    return LIB_NATIVE
+
+
+def use_native():
+    """Load the -march=native build instead of the portable one (for the CPU
+    timing leg; robots created before the switch keep the old library)."""
+    global _lib, _lib_path
+    build_native()
+    _lib, _lib_path = None, LIB_NATIVE
+    return lib()
+
+
 _lib = None
+_lib_path = None
 
 
 class _Params(C.Structure):
@@ -64,8 +88,9 @@ def _u64p(a):
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(LIB)
+        if _lib_path is None:
+            build()
+        L = C.CDLL(_lib_path or LIB)
         vp = C.c_void_p
         L.or_robot_create.restype = vp
         L.or_robot_create.argtypes = [C.POINTER(_Params), C.c_int, C.POINTER(C.c_uint8), C.POINTER(C.c_double)]
@@ -103,6 +128,7 @@ def lib():
                                        C.c_int, C.c_int, C.c_double, C.c_int, C.c_uint64, C.c_uint64,
                                        C.c_double, C.c_uint64, C.c_uint64, C.POINTER(C.c_int32)]
         L.or_num_threads.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -246,6 +272,11 @@ def pop_step(robots, n_steps):
 
 def num_threads():
     return lib().or_num_threads()
+
+
+def set_threads(n):
+    """Threads of the OpenMP loop over robots in pop_step."""
+    lib().or_set_threads(int(n))
 
 
 def encode(B, v):

@@ -566,6 +566,16 @@ int or_num_threads(void)
 #endif
 }
 
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* Fitness: displacement of the centre of mass along +x since the build
  * (equal node masses, so the COM is the node mean).  -inf when diverged. */
 double or_robot_fitness(const or_robot *R)

@@ -78,9 +78,11 @@ def load():
         raise RuntimeError("libsoftrobot.so is not built (run __graft_entry__.build()); "
                            "there is no fallback path")
     L = C.CDLL(LIB_PATH)
+    missing = [name for name in _SIGS if not hasattr(L, name)]
+    if missing:
+        raise RuntimeError("libsoftrobot.so lacks the entry points %s declared in include/softrobot.h; "
+                           "rebuild it (__graft_entry__.build())" % ", ".join(missing))
     for name, (args, res) in _SIGS.items():
-        if not hasattr(L, name):
-            continue
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res

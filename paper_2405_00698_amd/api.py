@@ -7,7 +7,7 @@ import ctypes as C
 import torch
 
 from . import _lib
-from ._lib import check
+from ._lib import SoftRobotError, check  # noqa: F401
 
 
 def _ptr(t, dtype, numel=None, name="tensor"):

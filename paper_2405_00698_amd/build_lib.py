@@ -34,6 +34,14 @@ def build(jobs=8):
         objs = list(ex.map(_compile, sources()))
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp])
+    # every kernel must fit one gfx950 CU (LDS, registers, scratch) before the
+    # library replaces the previous build
+    from paper_2405_00698_amd import codeobj
+    try:
+        codeobj.check(tmp, OBJ)
+    except Exception:
+        os.remove(tmp)
+        raise
     os.replace(tmp, LIB)
     return LIB
 

@@ -42,13 +42,15 @@ struct AArgs {
 // ALAG (exchange form): the position and adjoint reads of direction d + ALAG
 // are issued before direction d's arithmetic, which waits for its own two reads
 // only (ALAG 0: each read is waited for before the next is issued).
-template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0>
+// ONEBUF (recompute form): one position/adjoint buffer instead of two, with a
+// barrier at the start of each step, so that 12^3 robots fit in LDS.
+template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0, bool ONEBUF = false>
 __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     static_assert(ALAG == 0 || XCH, "pipelined reads are for the exchange form");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
-    constexpr int NBUF = XCH ? 1 : 2;
+    constexpr int NBUF = (XCH || ONEBUF) ? 1 : 2;
     constexpr int NQ = XCH ? 1 : NDIR;
     __shared__ float4 xs[NBUF][XL];
     __shared__ float4 lf[NBUF][XL];
@@ -134,8 +136,8 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         }
         float2 sc_next = A.n_steps > 0 ? A.sc[A.n_steps - 1] : make_float2(0.f, 0.f);
         for (int t = A.n_steps - 1; t >= 0; --t) {
-            const int b = XCH ? 0 : (t & 1);
-            if (XCH) __syncthreads();  // the previous step's readers are done with the buffers
+            const int b = NBUF == 1 ? 0 : (t & 1);
+            if (NBUF == 1) __syncthreads();  // the previous step's readers are done with the buffers
             const float2 sct = sc_next;
             if (t > 0) sc_next = A.sc[t - 1];
             float4 XRc[NPT], VPc[NPT];
@@ -599,9 +601,13 @@ struct AdjEntry {
     { NN, BS, k_adjoint<NN + 1, BS, false, X>, k_adjoint<NN + 1, BS, true, X> }
 #define SR_AEL(NN, BS, LG) \
     { NN, BS, k_adjoint<NN + 1, BS, false, true, LG>, k_adjoint<NN + 1, BS, true, true, LG> }
+// 12^3: the recompute form with one buffer (the exchange rows would need
+// 371 KB of LDS, two buffers 164 KB); its per-slot arrays spill to scratch.
+#define SR_AE1(NN, BS) \
+    { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, true>, k_adjoint<NN + 1, BS, true, false, 0, true> }
 const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
                          SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AEL(8, 768, 2),
-                         SR_AE(9, 1024, false), SR_AE(10, 704, false), SR_AE(11, 1024, false)};
+                         SR_AE(9, 1024, false), SR_AE(10, 704, false), SR_AE(11, 1024, false), SR_AE1(12, 1024)};
 
 }  // namespace
 

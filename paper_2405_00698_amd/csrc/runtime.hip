@@ -709,7 +709,11 @@ int pop_set_spring_params(sr_pop *pop, const float *k, const float *a, const flo
     if (!pop->built) return set_err(SR_ESTATE, "pop_set_spring_params before a build");
     int rc = ensure_counts(pop);
     if (rc) return rc;
-    if (phi) pop->phase = true;
+    if (phi && !pop->phase) {
+        // the captured step graphs hold the kernels without the phase plane
+        pop->phase = true;
+        clear_graphs(pop);
+    }
     if (pop->h_step > 0) pop->rec_valid = false;  // the recorded run used other parameters
     // kernels that rebuild the parameters from voxels would not see the new values
     pop->vox_ok = false;
@@ -849,8 +853,6 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     if (g_genome && (!genomes || !B)) return set_err(SR_EINVAL, "genome gradient needs the genomes and B");
     if (pop->p.zeta_spring != 0.f || pop->p.zeta_ground != 0.f)
         return set_err(SR_EUNSUPPORTED, "no adjoint with spring or ground dashpots");
-    for (const auto &gr : pop->groups)
-        if (gr.n > 11) return set_err(SR_EUNSUPPORTED, "no adjoint kernel for side %d", gr.n);
     const int K = pop->ck_every;
     int rc = ensure_adj_scratch(pop, K);
     if (rc) return rc;

@@ -268,9 +268,9 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 //   VOX    1 / 2: diagonal / all springs' parameters rebuilt from voxel terms
 //   SBX    one position buffer (one more barrier per step)
 //   LAG, LAGB, BSWP, FSWP  how the neighbour reads are pipelined (below)
-//   ROLL   direction loops left rolled (1) or unrolled by two (2), with no
-//          per-direction arrays: each iteration reads, computes and stores
-//          (offsets are wave-uniform)
+//   ROLL   0: direction loops fully unrolled; U > 0: left rolled and unrolled
+//          by U, with no per-direction arrays: each iteration reads, computes
+//          and stores one direction (offsets are wave-uniform)
 //
 // LAG (exchange variants, 16-byte reads): the neighbour reads of a slot are
 // issued back to back with at most LAG + 1 outstanding; the read LAG places
@@ -874,176 +874,101 @@ struct PersistEntry {
     size_t lds;
 };
 
-// variant code: exchange variant (0, 1, 2) + 4 when scheduling fences bound the
-// number of LDS loads in flight + 8 for 12-byte instead of 16-byte position loads
-// + 16 for the spring-dashpot kernels
+// Variant codes (the sum documented at pop_set_persist_variant): exchange
+// variant (0, 1, 2); + 4 scheduling fences bound the LDS loads in flight; + 8
+// 12-byte instead of 16-byte position loads; + 16 spring-dashpot kernels;
+// + 32 * VOX spring parameters of the face and body diagonals (VOX 1) or of
+// every direction (VOX 2) rebuilt from voxels each step; + 128 one position
+// buffer (one more barrier per step, less LDS); + 256 * LAG pipelined 16-byte
+// neighbour reads; + 4096 * (LB + 1) a separate backward lag; + 131072 / + 262144
+// software-pipelined backward / forward springs; + 2097152 rolled direction
+// loops with every parameter from voxels, + 4194304 * (U - 1) unrolled by U.
+// Every entry's LDS arrays must fit one CU's 160 KiB (checked at compile time
+// here, and for the code objects as built by a CPU test, since the compiler may
+// add LDS of its own).
+template <size_t B>
+constexpr size_t lds_ok() {
+    static_assert(B <= 160 * 1024, "persistent kernel configuration exceeds the 160 KiB of LDS per CU");
+    return B;
+}
 #define SR_PE(NN, BS, VAR, F, W)                                                                        \
     {                                                                                                   \
         NN, BS, VAR + 4 * F + 8 * (1 - W), k_persist<NN + 1, BS, VAR, F, false, false, W>,              \
-            k_persist<NN + 1, BS, VAR, F, true, false, W>, lds_bytes<NN + 1, BS, VAR>()                 \
+            k_persist<NN + 1, BS, VAR, F, true, false, W>, lds_ok<lds_bytes<NN + 1, BS, VAR>()>()                 \
     }
-// spring parameters of the face and body diagonals (VOX 1) or of every
-// direction (VOX 2) rebuilt from voxels each step: + 32 VOX; + 128 for one
-// position buffer (one more barrier per step, less LDS)
-#define SR_PV(NN, BS, VAR, VOX, SBX, F)                                                                    \
-    {                                                                                                        \
-        NN, BS, VAR + 4 * F + 32 * VOX + 128 * SBX,                                                          \
-            k_persist<NN + 1, BS, VAR, F, false, false, true, false, VOX, SBX>,                              \
-            k_persist<NN + 1, BS, VAR, F, true, false, true, false, VOX, SBX>,                               \
-            lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()                                                    \
-    }
-// pipelined 16-byte neighbour reads: + 256 * LAG
-#define SR_PL(NN, BS, VAR, F, LG)                                                                          \
-    {                                                                                                        \
-        NN, BS, VAR + 4 * F + 256 * LG,                                                                      \
-            k_persist<NN + 1, BS, VAR, F, false, false, true, false, 0, false, LG>,                          \
-            k_persist<NN + 1, BS, VAR, F, true, false, true, false, 0, false, LG>, lds_bytes<NN + 1, BS, VAR>() \
-    }
-// separate backward lag: + 4096 * (LB + 1)
-#define SR_PLB(NN, BS, F, LF, LB)                                                                          \
-    {                                                                                                        \
-        NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1),                                                      \
-            k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB>,                        \
-            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB>, lds_bytes<NN + 1, BS, 1>() \
-    }
-// software-pipelined backward springs: + 131072
 #define SR_PLS(NN, BS, F, LF, LB)                                                                          \
     {                                                                                                        \
         NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072,                                             \
             k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, true>,                  \
-            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, true>, lds_bytes<NN + 1, BS, 1>() \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, true>, lds_ok<lds_bytes<NN + 1, BS, 1>()>() \
     }
-// software-pipelined forward springs: + 262144
 #define SR_PLF(NN, BS, F, LF, LB, BSW)                                                                     \
     {                                                                                                        \
         NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072 * BSW + 262144,                              \
             k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, BSW, true>,             \
             k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, BSW, true>,              \
-            lds_bytes<NN + 1, BS, 1>()                                                                       \
+            lds_ok<lds_bytes<NN + 1, BS, 1>()>()                                                                       \
     }
-#define SR_PVLF(NN, BS, VOX, SBX, F, LF, LB, BSW)                                                            \
-    {                                                                                                        \
-        NN, BS, 1 + 4 * F + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1) + 131072 * BSW + 262144,       \
-            k_persist<NN + 1, BS, 1, F, false, false, true, false, VOX, SBX, LF, LB, BSW, true>,             \
-            k_persist<NN + 1, BS, 1, F, true, false, true, false, VOX, SBX, LF, LB, BSW, true>,              \
-            lds_bytes<NN + 1, BS, 1, false, VOX, SBX>()                                                      \
-    }
-// rolled direction loops (+2097152), every parameter from voxels
-#define SR_PR(NN, BS, VAR, SBX, F) SR_PRU(NN, BS, VAR, SBX, F, 1)
-// unrolled by two: + 4194304
 #define SR_PRU(NN, BS, VAR, SBX, F, U)                                                                       \
     {                                                                                                        \
         NN, BS, VAR + 4 * F + 64 + 128 * SBX + 2097152 + 4194304 * (U - 1),                                  \
             k_persist<NN + 1, BS, VAR, F, false, false, true, false, 2, SBX, 0, -1, false, false, U>,        \
             k_persist<NN + 1, BS, VAR, F, true, false, true, false, 2, SBX, 0, -1, false, false, U>,         \
-            lds_bytes<NN + 1, BS, VAR, false, 2, SBX>()                                                      \
-    }
-#define SR_PVLB(NN, BS, VOX, SBX, F, LF, LB)                                                              \
-    {                                                                                                        \
-        NN, BS, 1 + 4 * F + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1),                               \
-            k_persist<NN + 1, BS, 1, F, false, false, true, false, VOX, SBX, LF, LB>,                        \
-            k_persist<NN + 1, BS, 1, F, true, false, true, false, VOX, SBX, LF, LB>,                         \
-            lds_bytes<NN + 1, BS, 1, false, VOX, SBX>()                                                      \
+            lds_ok<lds_bytes<NN + 1, BS, VAR, false, 2, SBX>()>()                                                      \
     }
 #define SR_PVL(NN, BS, VAR, VOX, SBX, F, LG)                                                              \
     {                                                                                                        \
         NN, BS, VAR + 4 * F + 32 * VOX + 128 * SBX + 256 * LG,                                               \
             k_persist<NN + 1, BS, VAR, F, false, false, true, false, VOX, SBX, LG>,                          \
             k_persist<NN + 1, BS, VAR, F, true, false, true, false, VOX, SBX, LG>,                           \
-            lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()                                                    \
+            lds_ok<lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()>()                                                    \
     }
 // dashpot kernels carry the phase plane always (with a zero plane the results
-// are the same bits as without it); SR_PDL with pipelined reads (positions and
-// velocities)
+// are the same bits as without it); SR_PDF / SR_PDVF software-pipeline their
+// position and velocity reads
 #define SR_PD(NN, BS, VAR)                                                                              \
     {                                                                                                   \
         NN, BS, VAR + 16, k_persist<NN + 1, BS, VAR, false, true, false, true, true>,                   \
-            k_persist<NN + 1, BS, VAR, false, true, false, true, true>, lds_bytes<NN + 1, BS, VAR, true>() \
+            k_persist<NN + 1, BS, VAR, false, true, false, true, true>, lds_ok<lds_bytes<NN + 1, BS, VAR, true>()>() \
     }
 #define SR_PDF(NN, BS, LF, LB)                                                                              \
     {                                                                                                        \
         NN, BS, 1 + 16 + 256 * LF + 4096 * (LB + 1) + 131072 + 262144,                                       \
             k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB, true, true>,          \
             k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB, true, true>,          \
-            lds_bytes<NN + 1, BS, 1, true>()                                                                 \
+            lds_ok<lds_bytes<NN + 1, BS, 1, true>()>()                                                                 \
     }
 #define SR_PDVF(NN, BS, VOX, SBX, LF, LB)                                                                   \
     {                                                                                                        \
         NN, BS, 1 + 16 + 32 * VOX + 128 * SBX + 256 * LF + 4096 * (LB + 1) + 131072 + 262144,                \
             k_persist<NN + 1, BS, 1, false, true, false, true, true, VOX, SBX, LF, LB, true, true>,          \
             k_persist<NN + 1, BS, 1, false, true, false, true, true, VOX, SBX, LF, LB, true, true>,          \
-            lds_bytes<NN + 1, BS, 1, true, VOX, SBX>()                                                       \
-    }
-#define SR_PDL(NN, BS, LF, LB)                                                                         \
-    {                                                                                                    \
-        NN, BS, 1 + 16 + 256 * LF + 4096 * (LB + 1),                                                     \
-            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB>,                  \
-            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, false, LF, LB>,                  \
-            lds_bytes<NN + 1, BS, 1, true>()                                                             \
+            lds_ok<lds_bytes<NN + 1, BS, 1, true, VOX, SBX>()>()                                                       \
     }
 
 // The first entry of each side is its default configuration, the first one
-// without voxel terms the default when the spring parameters were set directly
-// (the fastest measured: 4096 robots of 10^3; 11^3 and 12^3 robots of an uneven
-// population).
+// without voxel terms the default when the spring parameters were set directly.
+// The table keeps, per side, the configurations a measured workload chose
+// (4096 robots of 10^3; the sides of the uneven population; the Table II model
+// at 5^3 and 8^3) and the plain one-chunk exchange as a cross-check of the
+// pipelined forms; the configurations measured slower are not compiled.
 const PersistEntry kPersist[] = {
-    SR_PLF(4, 128, 0, 3, 3, 1),  SR_PLF(5, 256, 0, 3, 3, 1),  SR_PLF(6, 384, 0, 3, 3, 1),  SR_PLF(7, 512, 0, 3, 3, 1),
-    SR_PL(4, 128, 1, 0, 4),   SR_PL(5, 256, 1, 0, 4),   SR_PL(6, 384, 1, 0, 4),   SR_PL(7, 512, 1, 0, 4),
-    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLS(10, 512, 0, 12, 3), SR_PRU(11, 896, 1, 1, 1, 3),
-    SR_PVL(11, 256, 1, 2, 1, 1, 4),
-    SR_PLF(10, 448, 0, 3, 3, 1),
-    SR_PLB(8, 768, 0, 12, 4), SR_PLB(9, 1024, 0, 12, 8),
-    SR_PRU(12, 768, 2, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 2), SR_PR(12, 1024, 2, 1, 1), SR_PV(12, 768, 2, 2, 1, 1),
-    SR_PE(11, 256, 1, 0, 1),  SR_PV(11, 256, 1, 1, 1, 1),  SR_PV(11, 896, 1, 2, 1, 1),
-    SR_PE(1, 64, 1, 0, 1),    SR_PE(2, 64, 1, 0, 1),    SR_PE(3, 64, 1, 0, 1),    SR_PE(4, 128, 1, 0, 1),  SR_PE(4, 64, 1, 0, 1),
-    SR_PE(4, 128, 0, 0, 1),   SR_PE(5, 256, 1, 0, 1),   SR_PE(5, 128, 1, 0, 1),   SR_PE(5, 256, 0, 0, 1),  SR_PE(6, 384, 1, 0, 1),
-    SR_PE(6, 192, 1, 0, 1),   SR_PE(6, 384, 0, 0, 1),   SR_PE(7, 512, 1, 0, 1),   SR_PE(7, 256, 1, 0, 1),  SR_PE(7, 512, 0, 0, 1),
-    SR_PE(8, 768, 0, 0, 0), SR_PE(8, 768, 0, 0, 1), SR_PE(8, 768, 1, 0, 0),   SR_PE(8, 768, 1, 0, 1),   SR_PE(8, 384, 1, 0, 1),   SR_PE(8, 256, 1, 0, 1),  SR_PE(8, 384, 1, 1, 1),
-    SR_PE(8, 256, 1, 1, 1),   SR_PE(8, 512, 0, 0, 1),   SR_PE(8, 256, 0, 0, 1),   SR_PE(9, 1024, 1, 0, 1), SR_PE(9, 512, 1, 0, 1),
-    SR_PE(9, 512, 1, 1, 1),   SR_PE(9, 1024, 0, 0, 1),  SR_PE(9, 512, 0, 0, 1),   SR_PE(10, 512, 1, 0, 1),
-    SR_PE(10, 448, 1, 1, 1),  SR_PE(10, 704, 1, 0, 1),  SR_PE(10, 1024, 1, 0, 1), SR_PE(10, 704, 0, 0, 1), SR_PE(10, 704, 2, 0, 1),
-    SR_PE(10, 448, 2, 0, 1),  SR_PE(10, 448, 0, 0, 1),  SR_PE(10, 512, 0, 0, 1),  SR_PE(10, 384, 1, 0, 1), SR_PE(11, 896, 1, 0, 1),
-    SR_PE(11, 896, 1, 1, 1),  SR_PE(11, 576, 1, 0, 1),  SR_PE(11, 576, 1, 1, 1),  SR_PE(11, 1024, 0, 0, 1), SR_PE(12, 768, 2, 0, 1),
-    SR_PE(12, 768, 2, 1, 1),  SR_PE(12, 768, 0, 0, 1),  SR_PE(12, 1024, 2, 0, 1), SR_PE(12, 1024, 2, 1, 1),
-    SR_PE(10, 256, 1, 0, 1),  SR_PE(9, 256, 1, 0, 1),   SR_PE(12, 256, 2, 0, 1),
-    // parameters rebuilt from voxels
-    SR_PV(10, 448, 1, 1, 0, 0),  SR_PV(10, 512, 1, 1, 0, 0),  SR_PV(10, 704, 1, 1, 0, 0),  SR_PV(10, 704, 1, 2, 0, 0),
-    SR_PV(10, 448, 1, 2, 0, 0),  SR_PV(10, 704, 1, 2, 0, 1),  SR_PV(11, 576, 2, 1, 0, 0),  SR_PV(11, 896, 2, 1, 0, 0),
-    SR_PV(11, 896, 2, 2, 0, 0),  SR_PV(11, 896, 2, 2, 0, 1),  SR_PV(11, 576, 2, 2, 0, 1),
-    SR_PV(11, 576, 1, 2, 1, 1),  SR_PV(12, 768, 2, 2, 1, 0),  SR_PV(12, 1024, 2, 2, 1, 1),
-    SR_PV(12, 576, 2, 2, 1, 1),  SR_PV(9, 1024, 1, 1, 0, 0),  SR_PV(8, 768, 1, 1, 0, 0),
-    // one wave per SIMD, many slots per thread
-    SR_PV(10, 256, 1, 2, 0, 1),  SR_PV(10, 256, 1, 1, 0, 1),  SR_PV(11, 256, 1, 2, 1, 1),  SR_PV(12, 256, 2, 2, 1, 1),
-    // pipelined neighbour reads
-    SR_PL(10, 448, 1, 0, 2),  SR_PL(10, 448, 1, 0, 4),  SR_PL(10, 448, 1, 0, 6),  SR_PL(10, 512, 1, 0, 4),
-    SR_PL(9, 1024, 1, 0, 4),  SR_PL(11, 256, 1, 0, 4),  SR_PL(8, 768, 1, 0, 8),   SR_PL(8, 768, 1, 0, 4),
-    SR_PL(9, 1024, 1, 0, 8),  SR_PE(10, 448, 1, 0, 1),
-    SR_PL(9, 512, 1, 0, 4),   SR_PL(8, 256, 1, 0, 4),   SR_PVL(10, 448, 1, 1, 0, 0, 4),  SR_PVL(10, 512, 1, 1, 0, 0, 4),
-    SR_PVL(10, 512, 1, 2, 0, 0, 4),  SR_PVL(11, 256, 1, 1, 1, 1, 4),
-    SR_PLB(10, 448, 0, 4, 0),  SR_PLB(10, 448, 0, 2, 0),  SR_PLB(10, 448, 0, 6, 0),  SR_PLB(10, 448, 0, 8, 0),
-    SR_PLB(10, 448, 0, 12, 0), SR_PLB(10, 512, 0, 4, 0),  SR_PLB(10, 512, 0, 6, 0),  SR_PLB(10, 448, 1, 4, 0),
-    SR_PLB(10, 448, 0, 12, 2), SR_PLB(10, 448, 1, 12, 0), SR_PL(8, 768, 1, 0, 12),
-    SR_PLB(9, 1024, 0, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 12, 4),
-    SR_PVLB(11, 256, 2, 1, 1, 12, 0), SR_PVLB(11, 256, 2, 1, 1, 4, 0),
-    SR_PLB(7, 512, 0, 12, 0), SR_PLB(6, 384, 0, 12, 0), SR_PLB(5, 256, 0, 12, 0), SR_PLB(4, 128, 0, 12, 0),
-    SR_PLS(8, 768, 0, 12, 4),  SR_PLB(10, 512, 0, 12, 0), SR_PLF(10, 512, 0, 3, 3, 1),
-    SR_PLS(9, 1024, 0, 12, 4), SR_PLF(8, 256, 0, 3, 3, 1),  SR_PLF(9, 512, 0, 3, 3, 1),
-    SR_PVLF(11, 896, 2, 1, 1, 3, 3, 1), SR_PVLF(11, 256, 1, 1, 1, 3, 3, 1),
-    SR_PR(12, 768, 2, 1, 1),  SR_PRU(12, 1024, 2, 1, 1, 2), SR_PRU(12, 512, 2, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 5),
-    SR_PRU(12, 768, 2, 1, 1, 7), SR_PRU(12, 768, 2, 1, 0, 3), SR_PRU(11, 576, 1, 1, 1, 3),
-    SR_PRU(11, 512, 1, 1, 1, 4), SR_PRU(11, 896, 1, 1, 1, 4),
+    // defaults
+    SR_PE(1, 64, 1, 0, 1),      SR_PE(2, 64, 1, 0, 1),      SR_PE(3, 64, 1, 0, 1),
+    SR_PLF(4, 128, 0, 3, 3, 1), SR_PLF(5, 256, 0, 3, 3, 1), SR_PLF(6, 384, 0, 3, 3, 1), SR_PLF(7, 512, 0, 3, 3, 1),
+    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLS(10, 512, 0, 12, 3),
+    SR_PRU(11, 896, 1, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 3),
+    // stored-parameter fallbacks of the voxel-rebuilt defaults, and the next best measured
+    SR_PE(11, 256, 1, 0, 1),    SR_PE(12, 768, 2, 0, 1),
+    SR_PLF(10, 448, 0, 3, 3, 1), SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRU(12, 768, 2, 1, 1, 2),
+    // plain one-chunk exchange (cross-check of the pipelined forms) and the recompute variant
+    SR_PE(4, 128, 1, 0, 1),     SR_PE(5, 256, 1, 0, 1),     SR_PE(6, 384, 1, 0, 1),     SR_PE(7, 512, 1, 0, 1),
+    SR_PE(8, 768, 1, 0, 1),     SR_PE(9, 1024, 1, 0, 1),    SR_PE(10, 512, 1, 0, 1),    SR_PE(10, 704, 0, 0, 1),
     // spring dashpots (Table II model)
-    SR_PDF(4, 128, 3, 3),   SR_PDF(5, 256, 3, 3),   SR_PDF(6, 384, 3, 3),   SR_PDF(7, 512, 3, 3),
-    SR_PDF(8, 768, 3, 3),   SR_PDF(9, 1024, 3, 3),  SR_PDVF(10, 704, 2, 1, 3, 3), SR_PD(9, 1024, 1),
-    SR_PDL(4, 128, 4, 4),   SR_PDL(5, 256, 4, 4),   SR_PDL(6, 384, 4, 4),   SR_PDL(7, 512, 4, 4),
-    SR_PDL(8, 768, 4, 4),
-    SR_PD(1, 64, 1),    SR_PD(2, 64, 1),    SR_PD(3, 64, 1),     SR_PD(4, 128, 1),   SR_PD(4, 128, 0),
-    SR_PD(5, 256, 1),   SR_PD(5, 256, 0),   SR_PD(6, 384, 1),    SR_PD(6, 384, 0),   SR_PD(7, 512, 1),
-    SR_PD(7, 512, 0),   SR_PD(8, 768, 1),   SR_PD(8, 768, 0),    SR_PD(9, 512, 1),
-    SR_PD(9, 512, 0),   SR_PD(10, 512, 1),  SR_PD(10, 448, 1),   SR_PD(10, 704, 1),  SR_PD(11, 512, 2),
-    SR_PD(11, 576, 2),  SR_PD(11, 896, 2),  SR_PD(12, 512, 0),   SR_PD(12, 768, 0),
-    SR_PDL(8, 768, 12, 0),  SR_PDL(5, 256, 12, 0),
-    SR_PDF(9, 512, 3, 3),   SR_PDVF(10, 512, 2, 1, 3, 3), SR_PDVF(10, 448, 2, 1, 3, 3), SR_PDVF(10, 512, 1, 1, 3, 3),
+    SR_PD(1, 64, 1),            SR_PD(2, 64, 1),            SR_PD(3, 64, 1),
+    SR_PDF(4, 128, 3, 3),       SR_PDF(5, 256, 3, 3),       SR_PDF(6, 384, 3, 3),       SR_PDF(7, 512, 3, 3),
+    SR_PDF(8, 768, 3, 3),       SR_PDF(9, 1024, 3, 3),      SR_PDVF(10, 704, 2, 1, 3, 3),
+    SR_PD(10, 512, 1),          SR_PD(11, 512, 2),          SR_PD(12, 512, 0),          SR_PD(8, 768, 1),
 };
 
 #define SR_REC(NN, BS, VAR) \
@@ -1067,32 +992,11 @@ const PersistEntry *find_persist(const PersistCfg &cfg) {
     return nullptr;
 }
 
-constexpr int kNumPersist = sizeof(kPersist) / sizeof(kPersist[0]);
-
-// A configuration is usable when both of its kernels (with and without the
-// phase plane) fit in one CU's LDS as compiled: the compiler may place
-// private arrays in LDS too, so the code object, not the formula, decides.
-bool entry_fits(const PersistEntry &e) {
-    static int state[kNumPersist] = {0};  // 0 unknown, 1 fits, 2 does not
-    const int i = (int)(&e - kPersist);
-    if (state[i] == 0) {
-        size_t lds = e.lds;
-        for (PersistFn f : {e.fn, e.fn_phase}) {
-            hipFuncAttributes at;
-            if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(f)) == hipSuccess && at.sharedSizeBytes > lds)
-                lds = at.sharedSizeBytes;
-        }
-        state[i] = lds <= 160 * 1024 ? 1 : 2;
-    }
-    return state[i] == 1;
-}
-
 }  // namespace
 
 bool persist_supported(const PersistCfg &cfg, bool phase) {
     (void)phase;
-    const PersistEntry *e = find_persist(cfg);
-    return e && entry_fits(*e);
+    return find_persist(cfg) != nullptr;
 }
 
 size_t persist_lds_bytes(const PersistCfg &cfg) {
@@ -1103,7 +1007,7 @@ size_t persist_lds_bytes(const PersistCfg &cfg) {
 int persist_list(int n, int32_t *blocks, int32_t *variants, int cap) {
     int cnt = 0;
     for (const auto &e : kPersist)
-        if (e.n == n && entry_fits(e)) {
+        if (e.n == n) {
             if (cnt < cap) {
                 if (blocks) blocks[cnt] = e.block;
                 if (variants) variants[cnt] = e.variant;
@@ -1115,7 +1019,7 @@ int persist_list(int n, int32_t *blocks, int32_t *variants, int cap) {
 
 int persist_default_block(int n, bool dash, bool vox, int *variant) {
     for (const auto &e : kPersist)
-        if (e.n == n && ((e.variant & 16) != 0) == dash && (vox || !(e.variant & 96)) && entry_fits(e)) {
+        if (e.n == n && ((e.variant & 16) != 0) == dash && (vox || !(e.variant & 96))) {
             *variant = e.variant;
             return e.block;
         }
@@ -1126,7 +1030,7 @@ hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo 
                              int grid, Planes pl, float4 *x, float4 *v, const float2 *sc, int n_steps,
                              uint8_t *diverged, SimConst c, hipStream_t st) {
     const PersistEntry *e = find_persist(cfg);
-    if (!e || !entry_fits(*e)) return hipErrorInvalidConfiguration;
+    if (!e) return hipErrorInvalidConfiguration;
     PArgs A;
     A.robots = robots;
     A.list = list;

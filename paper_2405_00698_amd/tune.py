@@ -1,8 +1,10 @@
 """Tuner for the persistent step kernel: for every grid side present in a
 population, times each compiled (workgroup size, exchange variant)
-configuration on the live population and keeps the fastest.  Results are
-cached in a JSON file keyed by (device name, side, population bucket, spring
-model, the library's configuration list for that side)."""
+configuration on the live population and keeps the fastest; then times the
+number of steps per launch (the whole call, or the call split into shorter
+launches) on the whole population.  Results are cached in a JSON file keyed by
+(device name, side, population bucket, spring model, the library's
+configuration list for that side)."""
 import hashlib
 import json
 import os
@@ -45,7 +47,8 @@ def _time(p, steps):
 
 
 def tune(pop, steps=200, cache_path=None, verbose=False):
-    """Tunes `pop` in place (it must be built); returns {side: (block, variant, seconds)}.
+    """Tunes `pop` in place (it must be built); returns {side: (block, variant, seconds)}
+    and leaves the chosen steps per launch (0: the whole call) in pop.steps_per_launch.
     With several grid sides each side is timed on a copy of its own robots, since
     a step of the whole population runs every side.  The population is reset to
     its build state afterwards."""
@@ -94,6 +97,28 @@ def tune(pop, steps=200, cache_path=None, verbose=False):
         pop.set_persist_variant(n, best[0], best[1])
         result[n] = best
         cache[key] = list(best)
+    # steps per launch, on the whole population with the configurations above
+    skey = "%s|spl|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
+                             ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())))
+    if skey in cache:
+        spl = int(cache[skey])
+    else:
+        cands = sorted({0, steps // 2, steps // 5} - {-1})
+        times = []
+        for c in cands:
+            if c < 0 or (0 < c < 20):
+                continue
+            pop.set_step_config(api._lib.SR_STEP_AUTO, 0, c)
+            t = _time(pop, steps)
+            if verbose:
+                print("steps per launch %s: %.4f s" % (c or "all", t), flush=True)
+            times.append((c, t))
+        best = min(times, key=lambda q: q[1])
+        whole = [q for q in times if q[0] == 0][0]
+        spl = 0 if whole[1] <= 1.03 * best[1] else best[0]
+        cache[skey] = spl
+    pop.set_step_config(api._lib.SR_STEP_AUTO, 0, spl)
+    pop.steps_per_launch = spl
     pop.reset()
     if cache_path:
         tmp = cache_path + ".tmp"

@@ -29,24 +29,92 @@ def _dJ(R, seed=0):
     return np.random.default_rng(seed).uniform(0.5, 1.5, size=R).astype(np.float32)
 
 
+TOL = 1e-3  # gradient tolerance: relative L2 per parameter group, and per component (below)
+
+
+def _component_excess(g, ref):
+    """Largest |g_i - ref_i| / (1e-3 max(|ref_i|, 1e-3 max|ref|)): at most 1 when
+    every component is within 1e-3 of its reference value, with a floor of
+    1e-6 of the group's largest gradient for components near zero."""
+    floor = 1e-3 * np.abs(ref).max()
+    return float((np.abs(g - ref) / (TOL * np.maximum(np.abs(ref), max(floor, 1e-300)))).max())
+
+
+def _compare(P, robots, dJ, steps, label, bound=TOL):
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in P.backward(torch.from_numpy(dJ).to(DEV)).items()}
+    M, S, mo, so = P.counts()
+    worst = 0.0
+    for r, R in robots:
+        J, gk, ga, gp = R.backward(steps, g=float(dJ[r]))
+        sl = slice(so[r], so[r + 1])
+        l2 = [_l2rel(g[key][sl], ref) for key, ref in (("k", gk), ("a", ga), ("phi", gp))]
+        cx = [_component_excess(g[key][sl], ref) for key, ref in (("k", gk), ("a", ga), ("phi", gp))]
+        say(label, "robot", r, "springs", S[r], "relative L2 (k, a, phi): %.1e %.1e %.1e" % tuple(l2),
+            " per-component excess: %.2f %.2f %.2f" % tuple(cx))
+        worst = max(worst, max(l2))
+        if bound is not None:
+            assert max(l2) <= bound, (label, r, l2)
+            assert max(cx) <= 1.0, (label, r, cx)
+    return worst
+
+
 def test_spring_gradients_match_oracle(orc):
     cls, w = voxel_population(C1, 51)
     steps, K = 200, 50
     P = gpu_population(C1, cls, w)
     P.record(K, steps)
     P.step(steps)
-    dJ = _dJ(len(C1))
-    g = {k: v.cpu().numpy().astype(np.float64) for k, v in P.backward(torch.from_numpy(dJ).to(DEV)).items()}
-    M, S, mo, so = P.counts()
-    robots = oracle_robots(orc, C1, cls, w)
-    errs = []
-    for r, R in enumerate(robots):
-        J, gk, ga, gp = R.backward(steps, g=float(dJ[r]))
-        sl = slice(so[r], so[r + 1])
-        e = (_l2rel(g["k"][sl], gk), _l2rel(g["a"][sl], ga), _l2rel(g["phi"][sl], gp))
-        errs.append(e)
-    say("per-robot relative L2 errors (k, a, phi):", [tuple("%.1e" % v for v in e) for e in errs])
-    assert max(max(e) for e in errs) < 1e-2
+    robots = list(enumerate(oracle_robots(orc, C1, cls, w)))
+    _compare(P, robots, _dJ(len(C1)), steps, "C1")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12])
+def test_spring_gradients_match_oracle_every_side(orc, n):
+    """Every adjoint kernel instance (the exchange forms up to 8^3, the
+    recompute forms of 9^3-11^3, the one-buffer 12^3 form) against the oracle's
+    adjoint at the contact horizon, 200 steps with gravity, ground and
+    friction.  Odd sides carry per-spring phases (the phase-plane kernels)."""
+    sides = [n] * 2
+    cls, w = voxel_population(sides, 80 + n)
+    steps, K = 200, 50
+    P = gpu_population(sides, cls, w)
+    robots = oracle_robots(orc, sides, cls, w)
+    if n % 2 == 1:
+        sp = P.springs()
+        phi = torch.from_numpy(np.random.default_rng(n).uniform(-3.0, 3.0, size=sp["k"].numel())
+                               .astype(np.float32)).to(DEV)
+        P.set_spring_params(None, None, phi)
+        M, S, mo, so = P.counts()
+        ph = phi.cpu().numpy().astype(np.float64)
+        for r, R in enumerate(robots):
+            R.set_springs(phi=ph[so[r]:so[r + 1]])
+    P.record(K, steps)
+    P.step(steps)
+    _compare(P, list(enumerate(robots)), _dJ(len(sides), n), steps, "side %d" % n)
+
+
+def test_c4_sample_gradients_match_oracle(orc):
+    """The differentiation workload (64 robots of 8^3 from random genomes,
+    FP32 build, checkpoint every 100 steps): four sampled robots against the
+    oracle at the contact horizon (200 steps, bound 1e-3), and at the full
+    2000 steps, where only the agreement is reported."""
+    from paper_2405_00698_amd.api import Population
+    R = 64
+    G = inputs.random_genomes(R, seed=1)
+    B = inputs.gaussian_B()
+    sample = [0, 21, 42, 63]
+    dJ = _dJ(R, 4)
+    for steps, bound in ((200, TOL), (2000, None)):
+        P = Population([8] * R)
+        P.build_from_genomes(torch.from_numpy(G).to(DEV), torch.from_numpy(B).to(DEV), SR_QUERY_FP32)
+        cls, wq = (t.cpu().numpy() for t in P.query())
+        P.record(100, steps)
+        P.step(steps)
+        robots = [(r, orc.Robot(8, cls[r * 512:(r + 1) * 512], wq[r * 512:(r + 1) * 512].astype(np.float64)))
+                  for r in sample]
+        worst = _compare(P, robots, dJ, steps, "C4 %d steps" % steps, bound)
+        say("C4 sample, %d steps: worst relative L2 %.2e" % (steps, worst))
+        P.close()
 
 
 def test_gradients_independent_of_checkpoint_interval():
@@ -88,7 +156,7 @@ def test_genome_gradient_matches_oracle(orc):
         go = go * float(dJ[r])
         e = _l2rel(gg[r], go)
         say("robot", r, "genome gradient relative L2 %.2e" % e)
-        assert e < 2e-2
+        assert e <= TOL
 
 
 def test_autograd_functions_route_through_the_adjoint():

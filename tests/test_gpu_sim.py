@@ -106,29 +106,12 @@ def test_plain_and_persistent_agree_bitwise():
     assert np.array_equal(xs[0][0], xs[1][0]) and np.array_equal(xs[0][1], xs[1][1])
 
 
-@pytest.mark.parametrize("n,configs", [(4, [(128, 1025), (128, 1), (128, 7169), (128, 410369)]),
-                                       (5, [(256, 1025), (256, 1), (256, 7169), (256, 410369)]),
-                                       (6, [(384, 1025), (384, 1), (384, 7169), (384, 410369)]),
-                                       (7, [(512, 1025), (512, 1), (512, 7169), (512, 410369)]),
-                                       (8, [(768, 1), (384, 1), (256, 1), (768, 0), (384, 5), (256, 5), (768, 8), (768, 9),
-                                           (768, 33), (768, 1025), (768, 2049), (768, 3073), (256, 1025), (768, 23553), (768, 154625), (768, 410369), (256, 410369)]),
-                                       (9, [(1024, 2049), (1024, 1), (1024, 33), (512, 1), (256, 1), (1024, 1025), (512, 1025), (1024, 39937),
-                                           (1024, 7169), (1024, 154625), (1024, 410369), (512, 410369)]),
-                                       (10, [(512, 1), (448, 1), (704, 1), (1024, 1), (704, 0), (704, 2), (448, 2),
-                                             (448, 0), (448, 5), (512, 0), (384, 1), (448, 33), (704, 33), (704, 65),
-                                             (448, 65), (704, 69), (256, 1), (256, 69), (256, 37), (448, 513), (448, 1025),
-                                             (448, 1537), (512, 1025), (448, 1057), (512, 1057), (512, 1089), (448, 5121), (448, 4609),
-                                             (448, 5633), (448, 6145), (448, 7169), (512, 5121), (512, 5633), (448, 5125),
-                                             (448, 15361), (512, 7169), (448, 7173), (512, 150529), (512, 410369), (448, 410369)]),
-                                       (11, [(256, 165), (896, 1), (256, 1), (896, 34), (576, 34), (896, 66), (896, 70), (576, 70),
-                                             (896, 197), (576, 197), (256, 197), (256, 1025), (256, 1189), (256, 1221), (256, 23749), (256, 7365),
-                                             (256, 5317), (256, 410533), (896, 410565), (896, 10485957), (576, 10485957),
-                                             (512, 14680261), (896, 14680261)]),
-                                       (12, [(768, 2), (768, 0), (1024, 2), (768, 6), (1024, 6), (768, 194), (768, 198),
-                                             (1024, 198), (576, 198), (256, 2), (256, 198), (1024, 2097350), (768, 2097350),
-                                             (1024, 6291654), (768, 6291654), (768, 10485958), (512, 10485958), (768, 18874566),
-                                             (768, 27263174), (768, 10485954)])])
-def test_persistent_variants_bitwise(n, configs):
+@pytest.mark.parametrize("n", list(range(1, 13)))
+def test_persistent_variants_bitwise(n):
+    """Every compiled base-model configuration of side n gives the bits of
+    its side's first configuration."""
+    from paper_2405_00698_amd import api
+    configs = [(b, v) for b, v in api.persist_configs(n) if not v & 16]
     sides = [n] * 4
     cls, w = voxel_population(sides, 17)
     ref = None
@@ -246,16 +229,16 @@ def test_voxel_rebuilt_parameters_follow_spring_parameter_changes():
     # kernels that rebuild spring parameters from voxels cannot see parameters
     # set directly; the population falls back to a stored-parameter kernel
     from paper_2405_00698_amd import SoftRobotError
-    sides = [10] * 2
+    sides = [11] * 2
     cls, w = voxel_population(sides, 27)
     P = gpu_population(sides, cls, w)
-    P.set_persist_variant(10, 448, 33)
+    P.set_persist_variant(11, 256, 1221)
     sp = P.springs()
     P.set_spring_params(sp["k"] * 1.5, None, None)
-    b, v = P.persist_variant(10)
+    b, v = P.persist_variant(11)
     assert not (v & 96)
     with pytest.raises(SoftRobotError):
-        P.set_persist_variant(10, 448, 33)
+        P.set_persist_variant(11, 256, 1221)
     Q = gpu_population(sides, cls, w)
     Q.set_spring_params(sp["k"] * 1.5, None, None)
     Q.set_step_config(SR_STEP_PLAIN)
@@ -286,3 +269,28 @@ def test_uneven_population_sampled_parity(orc):
         Rb = orc.Robot(n, cls[offs[r]:offs[r + 1]], w[offs[r]:offs[r + 1]].astype(np.float64))
         Rb.step(200)
         assert rel_err(xs[r], Rb.state()[0]) <= 1e-3, (r, n)
+
+
+def test_new_phases_reach_captured_step_graphs():
+    """Step graphs captured before per-spring phases were set must not be
+    replayed afterwards: the phase-plane kernels have to run.  The same run
+    with graphs off is the reference (same kernels, so the same bits)."""
+    sides = [4] * 3 + [6] * 2
+    cls, w = voxel_population(sides, 91)
+    outs = []
+    for graphs in (True, False):
+        P = gpu_population(sides, cls, w)
+        P.set_graphs(graphs)
+        P.step(100)
+        sp = P.springs()
+        phi = torch.from_numpy(np.random.default_rng(5).uniform(-3, 3, size=sp["k"].numel())
+                               .astype(np.float32)).to(DEV)
+        P.set_spring_params(None, None, phi)
+        P.reset()
+        P.step(100)
+        outs.append(P.state()[0].cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    # and the phases change the motion (the graph did not replay the old kernels)
+    P = gpu_population(sides, cls, w)
+    P.step(100)
+    assert not np.array_equal(P.state()[0].cpu().numpy(), outs[0])

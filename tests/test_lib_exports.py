@@ -100,3 +100,33 @@ def test_voxel_order_of_rebuilt_parameters_matches_mesh_ranges(tmp_path):
         assert cnt == len(want) and got == want, (dx, dy, dz, got, want)
     offs = [int(t) for t in lines[13].split()]
     assert offs == [((i & 1) - 1) + 11 * (((i >> 1) & 1) - 1) + 121 * ((i >> 2) - 1) for i in range(8)]
+
+
+def test_every_kernel_fits_one_cu(tmp_path):
+    """Every kernel of the built library, as the compiler emitted it (LDS it
+    added itself included), fits one gfx950 CU at the largest workgroup it
+    admits: group segment <= 160 KiB, VGPRs + AGPRs within each wave's share
+    of the 512-register file, bounded scratch, no dynamic stack, wave64.  The
+    step, recording and adjoint kernels of every grid side are among them."""
+    from paper_2405_00698_amd import codeobj, _lib
+    ks = codeobj.kernels(_lib.LIB_PATH, str(tmp_path))
+    assert not codeobj.violations(ks)
+    names = [k[".name"] for k in ks]
+    for stem in ("k_persist", "k_adjoint", "k_query", "k_build_mesh", "k_ga_child"):
+        assert any(stem in nm for nm in names), stem
+    # adjoint kernels for every side 1..12 (template argument N = n + 1)
+    for n in range(1, 13):
+        assert any("k_adjointILi%dE" % (n + 1) in nm for nm in names), n
+
+
+def test_resource_check_rejects_oversized_kernels():
+    from paper_2405_00698_amd import codeobj
+    ok = {".name": "k", ".max_flat_workgroup_size": 512, ".wavefront_size": 64, ".group_segment_fixed_size": 130000,
+          ".vgpr_count": 256, ".private_segment_fixed_size": 0, ".uses_dynamic_stack": False}
+    assert codeobj.violations([ok]) == []
+    assert codeobj.vgpr_budget(256) == 512 and codeobj.vgpr_budget(512) == 256 and codeobj.vgpr_budget(1024) == 128
+    for field, val in ((".group_segment_fixed_size", 160 * 1024 + 16), (".vgpr_count", 264),
+                       (".private_segment_fixed_size", 1 << 20), (".uses_dynamic_stack", True),
+                       (".wavefront_size", 32)):
+        assert len(codeobj.violations([dict(ok, **{field: val})])) == 1, field
+    assert any("workgroup 2048" in v for v in codeobj.violations([dict(ok, **{".max_flat_workgroup_size": 2048})]))
