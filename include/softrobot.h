@@ -54,6 +54,7 @@ extern "C" {
 #define SR_GENOME_LEN 8710 /* W1[64][64] b1[64] W2[64][64] b2[64] W3[6][64] b3[6] */
 #define SR_PE_M 32         /* rows of the encoding matrix B (Eq. (1)), d = 3 */
 #define SR_MAX_SIDE 12     /* largest grid side n */
+#define SR_NOALLOC_MAX_STEPS 65536 /* largest n_steps of pop_step_noalloc */
 
 /* Build precision of the genome query. */
 #define SR_QUERY_FP32 0 /* FP32 FMA throughout */
@@ -209,6 +210,20 @@ int pop_get_persist_variant(sr_pop *pop, int32_t n, int32_t *block, int32_t *var
  * x <- x + dt v.  All forces use the state of step n.  A robot whose state is non-finite or beyond
  * 1e3 n voxel lengths at the end of a launch is flagged diverged and frozen. */
 int pop_step(sr_pop *pop, int32_t n_steps);
+
+/* pop_step for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * steps, kernels and results (bit for bit) as pop_step, and like it
+ * asynchronous on the population's stream, but it calls no hipMalloc, hipFree
+ * or allocating runtime routine and captures no graph: the per-step time
+ * table lives in a static device array of SR_NOALLOC_MAX_STEPS entries
+ * (512 KiB per device, held until the process ends), and the kernels are
+ * launched directly.  n_steps above SR_NOALLOC_MAX_STEPS: SR_EINVAL.  Every
+ * call on one device shares that table: calls that overlap on one device
+ * (two populations stepped concurrently on different streams) race, so
+ * order them on one stream or with events.  Checkpoints go to the buffers
+ * pop_record allocated, as in pop_step. */
+int pop_step_noalloc(sr_pop *pop, int32_t n_steps);
 
 /* Puts every robot back at its build state (step 0, lattice positions, zero
  * velocity, no divergence flag), keeping the spring parameters; restarts a

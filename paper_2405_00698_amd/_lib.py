@@ -8,6 +8,7 @@ LIB_PATH = os.path.join(HERE, "libsoftrobot.so")
 
 SR_OK, SR_EINVAL, SR_ENOMEM, SR_EHIP, SR_ESTATE, SR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 SR_NO_GRAVITY, SR_NO_GROUND, SR_NO_ACTUATION, SR_WEIGHT_ACTUATION = 1, 2, 4, 8
+SR_NOALLOC_MAX_STEPS = 65536
 SR_QUERY_FP32, SR_QUERY_BF16 = 0, 1
 SR_STEP_AUTO, SR_STEP_PERSISTENT, SR_STEP_PLAIN = 0, 1, 2
 GENOME_LEN = 8710
@@ -48,6 +49,7 @@ _SIGS = {
     "pop_build_from_genomes": ([P, P, P, C.c_int32], C.c_int),
     "pop_set_step_config": ([P, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "pop_step": ([P, C.c_int32], C.c_int),
+    "pop_step_noalloc": ([P, C.c_int32], C.c_int),
     "pop_fitness": ([P, P], C.c_int),
     "pop_get_counts": ([P, P, P, P, P], C.c_int),
     "pop_get_voxels": ([P, P, P], C.c_int),

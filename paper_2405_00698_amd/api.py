@@ -93,6 +93,11 @@ class Population:
     def step(self, n_steps):
         check(_lib.load().pop_step(self.h, int(n_steps)))
 
+    def step_noalloc(self, n_steps):
+        """pop_step_noalloc: the same steps without any device allocation (at
+        most SR_NOALLOC_MAX_STEPS per call; calls on one device share its table)."""
+        check(_lib.load().pop_step_noalloc(self.h, int(n_steps)))
+
     def fitness(self, out=None):
         if out is None:
             out = torch.empty(self.R, dtype=torch.float32, device=self.device)

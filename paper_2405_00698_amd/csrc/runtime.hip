@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,37 @@ int set_err(int code, const char *fmt, ...) {
     va_end(ap);
     g_err = buf;
     return code;
+}
+}  // namespace
+
+// Step time table of pop_step_noalloc: (sin, cos)(w t_n) for up to
+// SR_NOALLOC_MAX_STEPS steps (512 KiB), one copy per device for the life of
+// the process.  Host code never passes this name to a kernel: it uses the
+// device address that hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) float2 scratch[SR_NOALLOC_MAX_STEPS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float2 *g_scratch[kMaxDevices] = {};
+
+// Resolves (once per device, with that device current) and returns the
+// device address of `scratch` on `dev`.
+int noalloc_table(int dev, float2 **out) {
+    if (dev < 0 || dev >= kMaxDevices) return set_err(SR_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return set_err(SR_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch[dev] = static_cast<float2 *>(p);
+    }
+    *out = g_scratch[dev];
+    return SR_OK;
 }
 }  // namespace
 
@@ -44,6 +76,7 @@ struct sr_pop {
     sr_sim_params p;
     SimConst c;
     hipStream_t st = nullptr;
+    int device = 0;  // the device that was current at pop_create
     int R = 0, max_side = 0;
     std::vector<RobotInfo> h_robots;
     RobotInfo *d_robots = nullptr;
@@ -307,7 +340,14 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
     for (int r = 0; r < n_robots; ++r)
         if (grid_side[r] < 1 || grid_side[r] > SR_MAX_SIDE)
             return set_err(SR_EINVAL, "grid_side[%d] = %d outside 1..%d", r, grid_side[r], SR_MAX_SIDE);
+    int dev = 0;
+    hipError_t de = hipGetDevice(&dev);
+    if (de != hipSuccess) return set_err(SR_EHIP, "hipGetDevice: %s", hipGetErrorString(de));
+    float2 *table = nullptr;
+    int trc = noalloc_table(dev, &table);  // resolve the no-allocation step table on this device
+    if (trc) return trc;
     sr_pop *pop = new sr_pop();
+    pop->device = dev;
     pop->p = *params;
     pop->c = make_sim_const(*params);
     pop->st = reinterpret_cast<hipStream_t>(stream);
@@ -520,15 +560,15 @@ namespace {
 // step kernels (persistent: one launch per size group and block of steps, the
 // groups on their own streams so they run side by side; plain: one launch per
 // step), then the step counter.  Used eagerly and under graph capture.
-int enqueue_steps(sr_pop *pop, int n_steps, hipStream_t st) {
+int enqueue_steps(sr_pop *pop, int n_steps, float2 *sc, hipStream_t st) {
     const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
-    HIPC(pop, launch_sincos(pop->sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, st));
+    HIPC(pop, launch_sincos(sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, st));
     const int spl = pop->spl > 0 ? pop->spl : n_steps;
     if (pop->mode == SR_STEP_PLAIN) {
         for (int t = 0; t < n_steps; ++t) {
             const int a = pop->cur, b = 1 - pop->cur;
             HIPC(pop, launch_plain_step(pop->d_robots, pop->R, pop->total_slots, pop->rows, pop->entries, pop->pl,
-                                        pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], pop->sc, t,
+                                        pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], sc, t,
                                         pop->phase, pop->diverged, pop->slot_robot, pop->c, st));
             pop->cur = b;
         }
@@ -548,7 +588,7 @@ int enqueue_steps(sr_pop *pop, int n_steps, hipStream_t st) {
                 hipStream_t sq = q == 0 ? st : pop->side[q - 1];
                 HIPC(pop, launch_persistent(gr.cfg, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count,
                                             gr.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur],
-                                            pop->sc + t0, cnt, pop->diverged, pop->c, sq));
+                                            sc + t0, cnt, pop->diverged, pop->c, sq));
             }
         }
         for (int q = 1; q < G; ++q) {
@@ -568,47 +608,13 @@ int pop_set_graphs(sr_pop *pop, int32_t enable) {
     return SR_OK;
 }
 
-int pop_step(sr_pop *pop, int32_t n_steps) {
-    CHECK_POP(pop);
-    if (!pop->built) return set_err(SR_ESTATE, "pop_step before a build");
-    if (n_steps < 0) return set_err(SR_EINVAL, "n_steps < 0");
-    if (n_steps == 0) return SR_OK;
-    int rc = ensure_sc(pop, n_steps);
-    if (rc) return rc;
-    const bool recording = pop->rec_valid && pop->ck_every > 0;
-    if (!recording) {
-        if (!pop->use_graphs) {
-            rc = enqueue_steps(pop, n_steps, pop->st);
-            if (rc) return rc;
-        } else {
-            const GraphKey key{n_steps, pop->mode == SR_STEP_PLAIN ? 1 : 0, pop->cur, pop->spl};
-            auto it = pop->graphs.find(key);
-            const int cur0 = pop->cur;
-            if (it == pop->graphs.end()) {
-                HIPC(pop, hipStreamBeginCapture(pop->cap, hipStreamCaptureModeThreadLocal));
-                rc = enqueue_steps(pop, n_steps, pop->cap);
-                hipGraph_t graph = nullptr;
-                hipError_t e2 = hipStreamEndCapture(pop->cap, &graph);
-                if (rc) {
-                    if (graph) (void)hipGraphDestroy(graph);
-                    return rc;
-                }
-                HIPC(pop, e2);
-                hipGraphExec_t exec = nullptr;
-                hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                HIPC(pop, e3);
-                it = pop->graphs.emplace(key, exec).first;
-            }
-            // the graph carries the buffer flips of the per-step form
-            pop->cur = cur0 ^ ((pop->mode == SR_STEP_PLAIN) ? (n_steps & 1) : 0);
-            HIPC(pop, hipGraphLaunch(it->second, pop->st));
-        }
-        pop->h_step += n_steps;
-        return SR_OK;
-    }
+namespace {
+// Steps with checkpoints: the time table in sc (n_steps entries), then blocks
+// of steps that end at every checkpoint, each checkpoint copied into the
+// buffers pop_record allocated.
+int recorded_steps(sr_pop *pop, int n_steps, float2 *sc) {
     const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
-    HIPC(pop, launch_sincos(pop->sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, pop->st));
+    HIPC(pop, launch_sincos(sc, pop->d_step, n_steps, omega_dt, pop->c.actuation, pop->st));
     const int K = pop->rec_valid ? pop->ck_every : 0;
     for (int t = 0; t < n_steps;) {
         const int64_t g = pop->h_step + t;  // step index at the start of this block
@@ -634,14 +640,14 @@ int pop_step(sr_pop *pop, int32_t n_steps) {
             for (int q = 0; q < len; ++q) {
                 const int a = pop->cur, b = 1 - pop->cur;
                 HIPC(pop, launch_plain_step(pop->d_robots, pop->R, pop->total_slots, pop->rows, pop->entries, pop->pl,
-                                            pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], pop->sc, t + q,
+                                            pop->xbuf[a], pop->vbuf[a], pop->xbuf[b], pop->vbuf[b], sc, t + q,
                                             pop->phase, pop->diverged, pop->slot_robot, pop->c, pop->st));
                 pop->cur = b;
             }
         } else {
             for (const auto &gr : pop->groups) {
                 HIPC(pop, launch_persistent(gr.cfg, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count,
-                                            gr.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->sc + t,
+                                            gr.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur], sc + t,
                                             len, pop->diverged, pop->c, pop->st));
             }
         }
@@ -651,6 +657,66 @@ int pop_step(sr_pop *pop, int32_t n_steps) {
         HIPC(pop, launch_check_div(pop->d_robots, pop->R, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->diverged,
                                    pop->c.lim, pop->st));
     HIPC(pop, launch_advance(pop->d_step, n_steps, pop->st));
+    pop->h_step += n_steps;
+    return SR_OK;
+}
+}  // namespace
+
+int pop_step(sr_pop *pop, int32_t n_steps) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_step before a build");
+    if (n_steps < 0) return set_err(SR_EINVAL, "n_steps < 0");
+    if (n_steps == 0) return SR_OK;
+    int rc = ensure_sc(pop, n_steps);
+    if (rc) return rc;
+    const bool recording = pop->rec_valid && pop->ck_every > 0;
+    if (recording) return recorded_steps(pop, n_steps, pop->sc);
+    if (!pop->use_graphs) {
+        rc = enqueue_steps(pop, n_steps, pop->sc, pop->st);
+        if (rc) return rc;
+    } else {
+        const GraphKey key{n_steps, pop->mode == SR_STEP_PLAIN ? 1 : 0, pop->cur, pop->spl};
+        auto it = pop->graphs.find(key);
+        const int cur0 = pop->cur;
+        if (it == pop->graphs.end()) {
+            HIPC(pop, hipStreamBeginCapture(pop->cap, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_steps(pop, n_steps, pop->sc, pop->cap);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(pop->cap, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            HIPC(pop, e2);
+            hipGraphExec_t exec = nullptr;
+            hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPC(pop, e3);
+            it = pop->graphs.emplace(key, exec).first;
+        }
+        // the graph carries the buffer flips of the per-step form
+        pop->cur = cur0 ^ ((pop->mode == SR_STEP_PLAIN) ? (n_steps & 1) : 0);
+        HIPC(pop, hipGraphLaunch(it->second, pop->st));
+    }
+    pop->h_step += n_steps;
+    return SR_OK;
+}
+
+int pop_step_noalloc(sr_pop *pop, int32_t n_steps) {
+    CHECK_POP(pop);
+    if (!pop->built) return set_err(SR_ESTATE, "pop_step_noalloc before a build");
+    if (n_steps < 0) return set_err(SR_EINVAL, "n_steps < 0");
+    if (n_steps > SR_NOALLOC_MAX_STEPS)
+        return set_err(SR_EINVAL, "pop_step_noalloc: n_steps %d exceeds its step table of %d steps", n_steps,
+                       SR_NOALLOC_MAX_STEPS);
+    if (n_steps == 0) return SR_OK;
+    float2 *sc = nullptr;
+    int rc = noalloc_table(pop->device, &sc);
+    if (rc) return rc;
+    // direct launches only: capturing and instantiating a graph may allocate
+    if (pop->rec_valid && pop->ck_every > 0) return recorded_steps(pop, n_steps, sc);
+    rc = enqueue_steps(pop, n_steps, sc, pop->st);
+    if (rc) return rc;
     pop->h_step += n_steps;
     return SR_OK;
 }

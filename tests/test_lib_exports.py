@@ -130,3 +130,27 @@ def test_resource_check_rejects_oversized_kernels():
                        (".wavefront_size", 32)):
         assert len(codeobj.violations([dict(ok, **{field: val})])) == 1, field
     assert any("workgroup 2048" in v for v in codeobj.violations([dict(ok, **{".max_flat_workgroup_size": 2048})]))
+
+
+def test_noalloc_step_allocates_nothing():
+    """pop_step_noalloc and what it calls contain no allocating HIP call and
+    capture no graph (a source check: the device table is a static array)."""
+    src = open(os.path.join(ROOT, "paper_2405_00698_amd", "csrc", "runtime.hip")).read()
+
+    def body(name):
+        i = src.index(name)
+        i = src.index("{", i)
+        depth, j = 0, i
+        while True:
+            depth += {"{": 1, "}": -1}.get(src[j], 0)
+            if depth == 0:
+                return src[i:j + 1]
+            j += 1
+
+    bad = re.compile(r"hipMalloc|hipFree|hipHostMalloc|dalloc|ensure_sc|ensure_adj|hipGraphInstantiate|"
+                     r"hipStreamBeginCapture|hipMemset|new |malloc\(")
+    for fn in ("int pop_step_noalloc(", "int recorded_steps(", "int enqueue_steps(", "int noalloc_table("):
+        b = body(fn)
+        assert not bad.search(b), (fn, bad.search(b).group(0))
+    assert "static __device__ __align__(256) float2 scratch[SR_NOALLOC_MAX_STEPS]" in src
+    assert "hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))" in src
