@@ -114,8 +114,11 @@ def lib():
         L.or_robot_backward.restype = C.c_double
         L.or_robot_backward.argtypes = [vp, C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 3
         L.or_robot_backward_z.restype = C.c_double
-        L.or_robot_backward_z.argtypes = [vp, C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 3
-        L.or_robot_dJdw.argtypes = [vp] + [C.POINTER(C.c_double)] * 4
+        L.or_robot_backward_z.argtypes = [vp, C.c_int, C.c_double] + [C.POINTER(C.c_double)] * 4
+        L.or_robot_backward_c.restype = C.c_double
+        L.or_robot_backward_c.argtypes = [vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
+        L.or_robot_dashpots.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.or_robot_dJdw.argtypes = [vp] + [C.POINTER(C.c_double)] * 5
         L.or_mlp_backward.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int,
                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.or_encode.argtypes = [C.POINTER(C.c_double)] * 3
@@ -249,18 +252,35 @@ class Robot:
         return J, gk, ga, gp
 
     def backward_z(self, n_steps, g=1.0):
-        """J and dJ/d(k, Zr, Zi) per spring, Z = k a e^{i phi} (k at fixed Z)."""
-        gk, gr, gi = (np.zeros(self.S) for _ in range(3))
-        J = lib().or_robot_backward_z(self.h, int(n_steps), float(g), _dp(gk), _dp(gr), _dp(gi))
-        return J, gk, gr, gi
+        """J, dJ/d(k, Zr, Zi) per spring, Z = k a e^{i phi} (k at fixed Z), and
+        dJ/dc per spring dashpot coefficient."""
+        gk, gr, gi, gc = (np.zeros(self.S) for _ in range(4))
+        J = lib().or_robot_backward_z(self.h, int(n_steps), float(g), _dp(gk), _dp(gr), _dp(gi), _dp(gc))
+        return J, gk, gr, gi, gc
 
-    def dJdw(self, gkz, gzr, gzi):
-        """dJ/dw per voxel from dJ/d(k, Zr, Zi) through the parallel-sum rule."""
+    def backward_c(self, n_steps, g=1.0):
+        """J and dJ/dc per spring dashpot coefficient (Table II model)."""
+        gc = np.zeros(self.S)
+        J = lib().or_robot_backward_c(self.h, int(n_steps), float(g), _dp(gc))
+        return J, gc
+
+    def dashpots(self, cd=None):
+        """The springs' dashpot coefficients; with cd, sets them first."""
+        if cd is not None:
+            cin = np.ascontiguousarray(cd, dtype=np.float64)
+            lib().or_robot_dashpots(self.h, None, _dp(cin))
+        out = np.zeros(self.S)
+        lib().or_robot_dashpots(self.h, _dp(out), None)
+        return out
+
+    def dJdw(self, gkz, gzr, gzi, gcd=None):
+        """dJ/dw per voxel from dJ/d(k, Zr, Zi, c) through the parallel-sum rule."""
         out = np.zeros(self.n ** 3)
         arr = [np.ascontiguousarray(t, dtype=np.float64) for t in (gkz, gzr, gzi)]
-        rc = lib().or_robot_dJdw(self.h, *[_dp(t) for t in arr], _dp(out))
+        gc = None if gcd is None else np.ascontiguousarray(gcd, dtype=np.float64)
+        rc = lib().or_robot_dJdw(self.h, *[_dp(t) for t in arr], None if gc is None else _dp(gc), _dp(out))
         if rc != 0:
-            raise ValueError("no genome gradient with dashpots on")
+            raise ValueError("the genome gradient with spring dashpots needs dJ/dc")
         return out
 
 
@@ -370,6 +390,6 @@ def robot_from_genome(genome, B, n, **params):
 def genome_fitness_grad(genome, B, n, n_steps, **params):
     """J = fitness after n_steps of the robot built from `genome`, and dJ/dgenome."""
     R = robot_from_genome(genome, B, n, **params)
-    J, gk, gr, gi = R.backward_z(n_steps)
-    dJdw = R.dJdw(gk, gr, gi)
+    J, gk, gr, gi, gc = R.backward_z(n_steps)
+    dJdw = R.dJdw(gk, gr, gi, gc)
     return J, mlp_backward(genome, B, n, dJdw)

@@ -626,18 +626,24 @@ double or_robot_energy(const or_robot *R)
 /* Gradient of J = g * fitness after n_steps from the robot's current state
  * with respect to every spring's parameters, by reverse accumulation through
  * each forward operation (every state stored).  Contact and friction branches
- * are the ones the forward run took.  The robot itself is not modified.
+ * are the ones the forward run took, and so is the clamp of the damped ground
+ * force at zero.  The robot itself is not modified.
  * Two parametrisations of the actuated rest length
  *   L = L0 (1 + a sin(w t + phi)) = L0 + L0 (Zr sin wt + Zi cos wt) / k,
  * Z = k a e^{i phi}, are reported: (gk, ga, gphi) = dJ/d(k, a, phi) and
- * (gkz, gzr, gzi) = dJ/d(k, Zr, Zi) (k at fixed Z); any output may be NULL.
- * Returns J; NaN when a spring or ground dashpot is on (no adjoint for them). */
+ * (gkz, gzr, gzi) = dJ/d(k, Zr, Zi) (k at fixed Z); gcd = dJ/dc per spring
+ * dashpot coefficient (k, a, phi at fixed c); any output may be NULL.
+ * With the dashpots (Table II model) a spring's force is
+ *   f = k (r - L) + c (v_j - v_i).d^
+ * and the ground's normal force N = k_ground (-z) - c_g v_z (clamped at zero),
+ * so the forces also depend on the velocities of the step: the reverse step
+ * adds dF/dv^T lambda_F to the velocity adjoint. */
 static double backward_impl(const or_robot *R, int n_steps, double g, double *gk, double *ga, double *gphi,
-                            double *gkz, double *gzr, double *gzi)
+                            double *gkz, double *gzr, double *gzi, double *gcd)
 {
     int M = R->M, S = R->S;
-    if (R->p.zeta_spring != 0.0 || R->p.zeta_ground != 0.0) return NAN;
     const or_params *p = &R->p;
+    double cg = 2.0 * p->zeta_ground * sqrt(p->k_ground * p->mass); /* ground damper, as in ground_normal */
     double m = p->mass, dt = p->dt;
     int ground = !(p->flags & OR_NO_GROUND);
     int act = !(p->flags & OR_NO_ACTUATION);
@@ -663,7 +669,7 @@ static double backward_impl(const or_robot *R, int n_steps, double g, double *gk
     double *lx = (double *)calloc(3 * M, sizeof(double));
     double *lv = (double *)calloc(3 * M, sizeof(double));
     double *lF = (double *)malloc(sizeof(double) * 3 * M);
-    double *acc = (double *)calloc(6 * (size_t)S, sizeof(double)); /* gk ga gphi gkz gzr gzi */
+    double *acc = (double *)calloc(7 * (size_t)S, sizeof(double)); /* gk ga gphi gkz gzr gzi gcd */
     /* terminal condition: dJ/dx_N = g/M e_x, dJ/dv_N = 0 */
     for (int i = 0; i < M; ++i) lx[3 * i] = g / M;
 
@@ -677,12 +683,14 @@ static double backward_impl(const or_robot *R, int n_steps, double g, double *gk
             for (int q = 0; q < 3; ++q) lvt[q] = lv[3 * i + q] + dt * lx[3 * i + q];
             /* v_{n+1} = damping * v'' */
             for (int q = 0; q < 3; ++q) lvt[q] *= p->damping;
-            /* friction v'' = P(v', z) */
+            /* friction v'' = P(v', N) with the normal force N of the step */
             for (int q = 0; q < 3; ++q) vp[q] = v[3 * i + q] + dt * F[3 * i + q] / m;
             double z = x[3 * i + 2];
-            if (ground && z < 0.0) {
-                double dv = p->mu * p->k_ground * (-z) * dt / m;
-                double dvs = p->mu_static * p->k_ground * (-z) * dt / m;
+            double N = ground ? ground_normal(R, z, v[3 * i + 2]) : 0.0;
+            double lN = 0.0; /* dJ/dN */
+            if (N > 0.0) {
+                double dv = p->mu * N * dt / m;
+                double dvs = p->mu_static * N * dt / m;
                 double u = sqrt(vp[0] * vp[0] + vp[1] * vp[1]);
                 if (u <= dv || u <= dvs) {
                     lvt[0] = 0.0;
@@ -690,8 +698,8 @@ static double backward_impl(const or_robot *R, int n_steps, double g, double *gk
                 } else {
                     double uh[2] = {vp[0] / u, vp[1] / u};
                     double dot = uh[0] * lvt[0] + uh[1] * lvt[1];
-                    /* d(dv)/dz = -mu k_ground dt / m and dP/d(dv) = -uh */
-                    lx[3 * i + 2] += (p->mu * p->k_ground * dt / m) * dot;
+                    /* dP/d(dv) = -uh and d(dv)/dN = mu dt / m */
+                    lN += -(p->mu * dt / m) * dot;
                     double c = dv / u;
                     double l0 = lvt[0] - c * (lvt[0] - uh[0] * dot);
                     double l1 = lvt[1] - c * (lvt[1] - uh[1] * dot);
@@ -704,8 +712,13 @@ static double backward_impl(const or_robot *R, int n_steps, double g, double *gk
                 lv[3 * i + q] = lvt[q];
                 lF[3 * i + q] = dt / m * lvt[q];
             }
-            /* ground normal dF_z/dz = -k_ground below the plane */
-            if (ground && z < 0.0) lx[3 * i + 2] += -p->k_ground * lF[3 * i + 2];
+            /* the normal force enters F_z; where it is not clamped,
+             * dN/dz = -k_ground and dN/dv_z = -c_g */
+            if (N > 0.0) {
+                lN += lF[3 * i + 2];
+                lx[3 * i + 2] += -p->k_ground * lN;
+                lv[3 * i + 2] += -cg * lN;
+            }
         }
         /* springs */
         double wt = 2.0 * OR_PI * p->act_freq * (double)step * dt;
@@ -727,9 +740,28 @@ static double backward_impl(const or_robot *R, int n_steps, double g, double *gk
                 lx[3 * i + q] += Ku;
                 lx[3 * j + q] -= Ku;
             }
-            double *A = acc + 6 * (size_t)s;
+            /* dashpot c (v_j - v_i).d^ along d^: its force on i is c w d^ with the
+             * rate w = (v_j - v_i).d^, so with D = (c / r) [(dv - w d^) du + w (u - du d^)]
+             * node i takes D and node j -D in lambda_x, and c du d^ and -c du d^ in
+             * lambda_v; dJ/dc = -w du */
+            double wr = 0.0, dvv[3];
+            for (int q = 0; q < 3; ++q) {
+                dvv[q] = v[3 * j + q] - v[3 * i + q];
+                wr += dvv[q] * dh[q];
+            }
+            if (R->cd[s] != 0.0) {
+                for (int q = 0; q < 3; ++q) {
+                    double D = R->cd[s] / r * ((dvv[q] - wr * dh[q]) * du + wr * (u[q] - du * dh[q]));
+                    lx[3 * i + q] += D;
+                    lx[3 * j + q] -= D;
+                    lv[3 * i + q] += R->cd[s] * du * dh[q];
+                    lv[3 * j + q] -= R->cd[s] * du * dh[q];
+                }
+            }
+            double *A = acc + 7 * (size_t)s;
             A[0] += -(r - L) * du;
             A[3] += -(r - R->L0[s]) * du;
+            A[6] += -wr * du;
             if (act) {
                 double gL = R->k[s] * du;
                 A[1] += gL * R->L0[s] * sn;
@@ -739,10 +771,10 @@ static double backward_impl(const or_robot *R, int n_steps, double g, double *gk
             }
         }
     }
-    double *out[6] = {gk, ga, gphi, gkz, gzr, gzi};
-    for (int q = 0; q < 6; ++q)
+    double *out[7] = {gk, ga, gphi, gkz, gzr, gzi, gcd};
+    for (int q = 0; q < 7; ++q)
         if (out[q])
-            for (int s = 0; s < S; ++s) out[q][s] = acc[6 * (size_t)s + q];
+            for (int s = 0; s < S; ++s) out[q][s] = acc[7 * (size_t)s + q];
     free(acc);
     free(xs); free(vs); free(F); free(tmp.x); free(tmp.v); free(lx); free(lv); free(lF);
     return J;
@@ -750,26 +782,43 @@ static double backward_impl(const or_robot *R, int n_steps, double g, double *gk
 
 double or_robot_backward(const or_robot *R, int n_steps, double g, double *gk, double *ga, double *gphi)
 {
-    return backward_impl(R, n_steps, g, gk, ga, gphi, NULL, NULL, NULL);
+    return backward_impl(R, n_steps, g, gk, ga, gphi, NULL, NULL, NULL, NULL);
 }
 
-double or_robot_backward_z(const or_robot *R, int n_steps, double g, double *gkz, double *gzr, double *gzi)
+double or_robot_backward_z(const or_robot *R, int n_steps, double g, double *gkz, double *gzr, double *gzi,
+                           double *gcd)
 {
-    return backward_impl(R, n_steps, g, NULL, NULL, NULL, gkz, gzr, gzi);
+    return backward_impl(R, n_steps, g, NULL, NULL, NULL, gkz, gzr, gzi, gcd);
 }
 
-/* dJ/dw for every voxel from the per-spring gradients dJ/d(k, Zr, Zi) through
- * the sum rule: voxel v adds k_c w to k_s and k_c w amp_v e^{i ph_v} to Z_s of
- * each of its springs, so
+/* dJ/dc per spring dashpot coefficient (with the (k, a, phi) gradients), for
+ * the finite-difference pin of the dashpot terms. */
+double or_robot_backward_c(const or_robot *R, int n_steps, double g, double *gcd)
+{
+    return backward_impl(R, n_steps, g, NULL, NULL, NULL, NULL, NULL, NULL, gcd);
+}
+
+/* The dashpot coefficients of every spring (in and out), for the same pin. */
+void or_robot_dashpots(or_robot *R, double *cd_out, const double *cd_in)
+{
+    if (cd_out) memcpy(cd_out, R->cd, sizeof(double) * R->S);
+    if (cd_in) memcpy(R->cd, cd_in, sizeof(double) * R->S);
+}
+
+/* dJ/dw for every voxel from the per-spring gradients dJ/d(k, Zr, Zi, c)
+ * through the sum rule: voxel v adds k_c w to k_s, k_c w amp_v e^{i ph_v} to Z_s
+ * and zeta sqrt(2 m k_c w) to the dashpot c_s of each of its springs, so
  *   dJ/dw_v = sum_{s of v} k_c dJ/dk_s + dRe(.)/dw dJ/dZr_s + dIm(.)/dw dJ/dZi_s
+ *             + zeta sqrt(2 m k_c w) / (2 w) dJ/dc_s
  * with, for the base model (amp, ph fixed per class),
  *   d(k_c w a_c e^{i phi_c})/dw = k_c a_c e^{i phi_c},
  * and for the Table II model (amp = w a_c, ph = w phi_c),
  *   d(k_c a_c w^2 e^{i w phi_c})/dw = k_c a_c (2 w + i w^2 phi_c) e^{i w phi_c}.
- * Returns -1 when a dashpot is on (its coefficient also depends on w). */
-int or_robot_dJdw(const or_robot *R, const double *gkz, const double *gzr, const double *gzi, double *dJdw)
+ * gcd may be NULL when the spring dashpots are off. */
+int or_robot_dJdw(const or_robot *R, const double *gkz, const double *gzr, const double *gzi, const double *gcd,
+                  double *dJdw)
 {
-    if (R->p.zeta_spring != 0.0 || R->p.zeta_ground != 0.0) return -1;
+    if (R->p.zeta_spring != 0.0 && !gcd) return -1;
     int nv = R->n * R->n * R->n;
     for (int v = 0; v < nv; ++v) dJdw[v] = 0.0;
     for (int s = 0; s < R->S; ++s) {
@@ -786,6 +835,8 @@ int or_robot_dJdw(const or_robot *R, const double *gkz, const double *gzr, const
                 dzi = kc * ac * sin(pc);
             }
             dJdw[v] += kc * gkz[s] + dzr * gzr[s] + dzi * gzi[s];
+            if (R->p.zeta_spring != 0.0 && w > 0.0)
+                dJdw[v] += R->p.zeta_spring * sqrt(2.0 * R->p.mass * kc * w) / (2.0 * w) * gcd[s];
         }
     }
     return 0;
