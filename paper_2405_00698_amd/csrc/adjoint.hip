@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     const float dx = Y.x - Xr[k].x, dy = Y.y - Xr[k].y, dz = Y.z - Xr[k].z;
                     const float ux = LJ.x - LF[k].x, uy = LJ.y - LF[k].y, uz = LJ.z - LF[k].z;
                     const float r2 = len2(dx, dy, dz);
-                    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+                    const float ir = __builtin_amdgcn_rsqf(r2);
                     float kL = fmaf(pa[k][d], sct.x, pk[k][d] * L0d(c, d));
                     if (PHASE) kL = fmaf(pb[k][d], sct.y, kL);
                     const float c1 = fmaf(-kL, ir, pk[k][d]);
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                         const float dx = Xr[k].x - Y.x, dy = Xr[k].y - Y.y, dz = Xr[k].z - Y.z;
                         const float ux = LF[k].x - LI.x, uy = LF[k].y - LI.y, uz = LF[k].z - LI.z;
                         const float r2 = len2(dx, dy, dz);
-                        const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+                        const float ir = __builtin_amdgcn_rsqf(r2);
                         float kL = fmaf(qa[k][d], sct.x, qk[k][d] * L0d(c, d));
                         if (PHASE) kL = fmaf(qb[k][d], sct.y, kL);
                         const float c1 = fmaf(-kL, ir, qk[k][d]);

@@ -303,11 +303,18 @@ __global__ __launch_bounds__(BT) void k_build_mesh(BuildArgs A) {
         }
     }
 
-    // 9. initial state: lattice positions with the lowest node on z = 0
+    // 9. initial state: lattice positions with the lowest node on z = 0.  An
+    // absent lattice point sits far outside the robot (2e4 m plus its lattice
+    // offset, beyond the 1e4 m ghost slots): the step kernels evaluate every
+    // stencil spring, and an absent one (zero parameters) then never meets a
+    // zero length.
     const int zc = M > 0 ? zmin_c : 0;
     for (int s = tid; s < SL; s += BT) {
         int a = s % N, b = (s / N) % N, c = s / (N * N);
-        float4 p = make_float4(A.voxel_len * a, A.voxel_len * b, A.voxel_len * (c - zc), nid[s] >= 0 ? 1.f : 0.f);
+        const bool here = nid[s] >= 0;
+        const float far = here ? 0.f : 2e4f;
+        float4 p = make_float4(far + A.voxel_len * a, far + A.voxel_len * b, far + A.voxel_len * (c - zc),
+                               here ? 1.f : 0.f);
         const int g = ri.slot_base + s;
         A.x0[g] = p;
         A.x[g] = p;

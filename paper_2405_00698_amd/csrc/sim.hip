@@ -243,6 +243,124 @@ constexpr bool rdir_matches() {
 }
 static_assert(rdir_matches(), "run-time direction geometry must equal the stencil table");
 
+template <int V>
+struct IC {
+    static constexpr int value = V;
+};
+
+// Balanced slot plan (CLS kernels).  The lattice slots are cut into runs of 64
+// in slot order, one wave each.  A run that lies wholly in the top plane
+// (c = N - 1) has no forward spring that steps up in z (directions 4..12: their
+// upper ends would lie above the lattice), and one wholly in the bottom plane
+// (c = 0) no backward spring of those directions (their lower ends would lie
+// below it), so such runs skip those directions: they are light in the forward
+// phase of a step (top) or in the backward-and-update phase (bottom).  The
+// runs are dealt to the (slot index k, wave w) places of a workgroup, wave w
+// running on SIMD w mod 4, so that the SIMDs carry equal work in each phase:
+// every light run goes where the larger of the two phase maxima is smallest
+// (exhaustively over the few light runs), after the runs are spread as evenly
+// as the places allow.  Estimated work per run, in VALU instructions: forward
+// 14 per direction, backward 6 per direction plus 25 for the node update.
+enum { RUN_FULL = 0, RUN_TOP = 1, RUN_BOTTOM = 2 };
+
+template <int N>
+__host__ __device__ constexpr int run_class(int u) {
+    constexpr int SL = N * N * N, P = N * N;
+    const int first = 64 * u, last = (64 * u + 63 < SL ? 64 * u + 63 : SL - 1);
+    return last < P ? RUN_BOTTOM : (first >= SL - P ? RUN_TOP : RUN_FULL);
+}
+
+template <int N, int BS>
+struct SlotPlan {
+    static constexpr int SL = N * N * N, W = BS / 64, NPT = (SL + BS - 1) / BS, U = (SL + 63) / 64;
+    int unit[NPT][W];  // run held by place (k, w); -1: none
+};
+
+template <int N, int BS>
+constexpr SlotPlan<N, BS> make_slot_plan() {
+    using P = SlotPlan<N, BS>;
+    constexpr int U = P::U, W = P::W, NPT = P::NPT;
+    constexpr int FF = 13 * 14, FB = 13 * 6 + 25, TF = 4 * 14, BB = 4 * 6 + 25;
+    SlotPlan<N, BS> plan{};
+    int cap[4] = {0, 0, 0, 0}, cnt[4] = {0, 0, 0, 0};
+    for (int w = 0; w < W; ++w) cap[w % 4] += NPT;
+    for (int i = 0; i < U; ++i) {  // runs per SIMD, as even as the places allow
+        int best = -1;
+        for (int s = 0; s < 4; ++s)
+            if (cnt[s] < cap[s] && (best < 0 || cnt[s] < cnt[best])) best = s;
+        ++cnt[best];
+    }
+    int light[U > 0 ? U : 1] = {}, nl = 0;
+    for (int u = 0; u < U; ++u)
+        if (run_class<N>(u) != RUN_FULL) light[nl++] = u;
+    int combos = 1;
+    for (int i = 0; i < nl; ++i) combos *= 4;
+    int best_code = 0, best_cost = 1 << 30;
+    for (int code = 0; code < combos; ++code) {
+        int nlt[4] = {0, 0, 0, 0}, f[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+        bool ok = true;
+        for (int i = 0, c = code; i < nl; ++i, c /= 4) {
+            const int s = c % 4;
+            if (++nlt[s] > cnt[s]) ok = false;
+            const bool top = run_class<N>(light[i]) == RUN_TOP;
+            f[s] += top ? TF : FF;
+            b[s] += top ? FB : BB;
+        }
+        if (!ok) continue;
+        int mf = 0, mb = 0;
+        for (int s = 0; s < 4; ++s) {
+            f[s] += (cnt[s] - nlt[s]) * FF;
+            b[s] += (cnt[s] - nlt[s]) * FB;
+            mf = f[s] > mf ? f[s] : mf;
+            mb = b[s] > mb ? b[s] : mb;
+        }
+        if (mf + mb < best_cost) {
+            best_cost = mf + mb;
+            best_code = code;
+        }
+    }
+    // runs of each SIMD: its light runs, then full runs in slot order
+    int simd_of[U > 0 ? U : 1] = {};
+    int used[4] = {0, 0, 0, 0};
+    for (int i = 0, c = best_code; i < nl; ++i, c /= 4) {
+        simd_of[light[i]] = c % 4;
+        ++used[c % 4];
+    }
+    for (int u = 0; u < U; ++u) {
+        if (run_class<N>(u) != RUN_FULL) continue;
+        int s = 0;
+        while (used[s] >= cnt[s]) ++s;
+        simd_of[u] = s;
+        ++used[s];
+    }
+    for (int k = 0; k < NPT; ++k)
+        for (int w = 0; w < W; ++w) plan.unit[k][w] = -1;
+    for (int u = 0; u < U; ++u) {
+        const int s = simd_of[u];
+        bool placed = false;
+        for (int k = 0; k < NPT && !placed; ++k)
+            for (int w = s; w < W && !placed; w += 4)
+                if (plan.unit[k][w] < 0) {
+                    plan.unit[k][w] = u;
+                    placed = true;
+                }
+    }
+    return plan;
+}
+
+// every run placed exactly once
+template <int N, int BS>
+constexpr bool slot_plan_ok() {
+    constexpr auto p = make_slot_plan<N, BS>();
+    int seen[SlotPlan<N, BS>::U] = {};
+    for (int k = 0; k < SlotPlan<N, BS>::NPT; ++k)
+        for (int w = 0; w < SlotPlan<N, BS>::W; ++w)
+            if (p.unit[k][w] >= 0) ++seen[p.unit[k][w]];
+    for (int u = 0; u < SlotPlan<N, BS>::U; ++u)
+        if (seen[u] != 1) return false;
+    return true;
+}
+
 template <bool WIDEV>
 struct VoxT {
     typedef float2 T;
@@ -284,8 +402,9 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 // coefficient as soon as it is computed).
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
           int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false,
-          int ROLL = 0>
+          int ROLL = 0, bool CLS = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    static_assert(!CLS || (VAR == 1 && ROLL == 0), "the balanced slot plan is a form of the one-chunk exchange");
     static_assert(ROLL == 0 || (VAR >= 1 && VOX == 2 && !DASH && !REC && WIDE && LAG == 0 && !FSWP && !BSWP),
                   "the rolled direction loop is a form of the exchange with every parameter from voxels");
     static_assert(!FSWP || (WIDE && VAR == 1 && LAG > 0),
@@ -312,6 +431,31 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     __shared__ int bad;
     const int tid = threadIdx.x;
     const SimConst c = A.c;
+    // the lattice slot of each of this thread's NPT places: slot tid + k BS,
+    // or (CLS) lane tid mod 64 of the run the balanced plan gives the wave;
+    // top / bot: the wave's run lies in the top / bottom plane
+    int sk[NPT];
+    bool lk[NPT], topk[NPT], botk[NPT];
+    {
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            if constexpr (CLS) {
+                static_assert(slot_plan_ok<N, BS>(), "every run placed once");
+                constexpr SlotPlan<N, BS> plan = make_slot_plan<N, BS>();
+                const int u = plan.unit[k][w];
+                sk[k] = 64 * u + (tid & 63);
+                lk[k] = u >= 0 && sk[k] < SL;
+                topk[k] = u >= 0 && run_class<N>(u) == RUN_TOP;
+                botk[k] = u >= 0 && run_class<N>(u) == RUN_BOTTOM;
+            } else {
+                sk[k] = tid + k * BS;
+                lk[k] = sk[k] < SL;
+                topk[k] = false;
+                botk[k] = false;
+            }
+        }
+    }
 
     for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
         const int r = A.list[q];
@@ -345,8 +489,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
         float pd[NPT][DASH ? NDIR : 1], qd[NPT][DASH ? NQ : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int s = tid + k * BS;
-            const bool live = s < SL;
+            const int s = sk[k];
+            const bool live = lk[k];
             const int sc_ = live ? s : 0;
             const float4 X = A.x[base + sc_];
             const float4 V = A.v[base + sc_];
@@ -398,8 +542,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
             if (VAR == 0) {
 #pragma unroll
                 for (int k = 0; k < NPT; ++k) {
-                    const int s = tid + k * BS;
-                    if (s < SL) {
+                    const int s = sk[k];
+                    if (lk[k]) {
 #pragma unroll
                         for (int d = 0; d < NDIR; ++d) {
                             const float3 Y = ldx<WIDE>(xc + s + (PAD + dir_off(d, N)));
@@ -448,8 +592,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     const int d1 = (ch + 1) * NDC < NDIR ? (ch + 1) * NDC : NDIR;
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
-                        const int s = tid + k * BS;
-                        if (s < SL) {
+                        const int s = sk[k];
+                        if (lk[k]) {
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
                             int vo = PAD + s;
@@ -484,8 +628,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     __syncthreads();
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
-                        const int s = tid + k * BS;
-                        if (s < SL) {
+                        const int s = sk[k];
+                        if (lk[k]) {
                             const float4 *xs = xc + s;
                             const float *cs = coef + s;
 #pragma unroll ROLL
@@ -510,43 +654,131 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                     const int d1 = (ch + 1) * NDC < NDIR ? (ch + 1) * NDC : NDIR;
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
-                        const int s = tid + k * BS;
-                        if (s < SL) {
+                        const int s = sk[k];
+                        if (lk[k]) {
                             // every neighbour read of this slot is issued before any use;
                             // addresses are one base plus non-negative immediates
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
-                            if constexpr (FSWP) {
-                                float4 Q[NDIR], QV[DASH ? NDIR : 1];
+                            // forward springs of directions d0 .. DE - 1: a run in the top
+                            // plane has only the four that stay in the plane
+                            auto forward = [&](auto DEC) {
+                                constexpr int DE = decltype(DEC)::value;
+                                const int de = DE < d1 ? DE : d1;
+                                if constexpr (FSWP) {
+                                    float4 Q[NDIR], QV[DASH ? NDIR : 1];
+                                    float4 Vx[VOX > 0 ? 8 : 1];
+                                    if constexpr (VOX > 0) {
+                                        // re-read every step (see below)
+                                        int vo = PAD + s;
+                                        __asm__ volatile("" : "+v"(vo));
+    #pragma unroll
+                                        for (int i = 0; i < 8; ++i) Vx[i] = vox4(vv[vo + vox_off(i, N)]);
+                                    }
+    #pragma unroll
+                                    for (int d = 0; d < NDIR; ++d)
+                                        if (d >= d0 && d < de && d < d0 + LAG) {
+                                            Q[d] = xs[PAD + dir_off(d, N)];
+                                            if constexpr (DASH) QV[DASH ? d : 0] = vb[s + PAD + dir_off(d, N)];
+                                        }
+    #pragma unroll
+                                    for (int d = 0; d < NDIR; ++d) {
+                                        if (d < d0 || d >= de) continue;
+                                        const int e = d + LAG < de ? d + LAG : d0;
+                                        if (d + LAG < de) {
+                                            Q[e] = xs[PAD + dir_off(e, N)];
+                                            if constexpr (DASH) QV[DASH ? e : 0] = vb[s + PAD + dir_off(e, N)];
+                                        }
+                                        keep_w(Q[d].w);
+                                        if constexpr (DASH) keep_w(QV[DASH ? d : 0].w);
+                                        const float dx = Q[d].x - xr[k].x, dy = Q[d].y - xr[k].y, dz = Q[d].z - xr[k].z;
+                                        float kk, al, be, cd;
+                                        if (from_vox(VOX, d)) {
+                                            float4 sm = Vx[VOX > 0 ? vox_idx(d, 0) : 0];
+    #pragma unroll
+                                            for (int i = 1; i < vox_cnt(d); ++i) {
+                                                const float4 u = Vx[VOX > 0 ? vox_idx(d, i) : 0];
+                                                sm.x = add_nf(sm.x, u.x);
+                                                sm.y = add_nf(sm.y, u.y);
+                                                if (PHASE) sm.z = add_nf(sm.z, u.z);
+                                                if (DASH) sm.w = add_nf(sm.w, u.w);
+                                            }
+                                            kk = sm.x;
+                                            al = mul_nf(sm.y, L0d(c, d));
+                                            be = PHASE ? mul_nf(sm.z, L0d(c, d)) : 0.f;
+                                            cd = sm.w;
+                                        } else {
+                                            kk = pk[k][d];
+                                            al = pa[k][d];
+                                            be = PHASE ? pb[k][d] : 0.f;
+                                            cd = DASH ? pd[k][DASH ? d : 0] : 0.f;
+                                        }
+                                        float cf;
+                                        if constexpr (DASH) {
+                                            const float4 W = QV[DASH ? d : 0];
+                                            cf = spring_coef_d<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz),
+                                                                      cd,
+                                                                      rate(W.x - vr[k].x, W.y - vr[k].y, W.z - vr[k].z, dx, dy, dz));
+                                        } else {
+                                            cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz));
+                                        }
+                                        cs[(d - d0) * CL + PAD] = cf;
+                                        Ff[k].x = fmaf(cf, dx, Ff[k].x);
+                                        Ff[k].y = fmaf(cf, dy, Ff[k].y);
+                                        Ff[k].z = fmaf(cf, dz, Ff[k].z);
+                                    }
+                                } else {
+                                float3 Y[NDIR], VY[DASH ? NDIR : 1];
+                                float Wk[NDIR], Wv[DASH ? NDIR : 1];
+                                if constexpr (WIDE && LAG > 0) {
+    #pragma unroll
+                                    for (int d = d0; d < de; ++d) {
+                                        const float4 q = xs[PAD + dir_off(d, N)];
+                                        Y[d] = make_float3(q.x, q.y, q.z);
+                                        Wk[d] = q.w;
+                                        if constexpr (DASH) {
+                                            const float4 u = vb[s + PAD + dir_off(d, N)];
+                                            VY[DASH ? d : 0] = make_float3(u.x, u.y, u.z);
+                                            Wv[DASH ? d : 0] = u.w;
+                                        }
+                                        if (d - LAG >= d0) {
+                                            keep_w(Wk[d - LAG >= 0 ? d - LAG : 0]);
+                                            if constexpr (DASH) keep_w(Wv[DASH && d - LAG >= 0 ? d - LAG : 0]);
+                                        }
+                                    }
+                                } else {
+    #pragma unroll
+                                    for (int d = d0; d < de; ++d) Y[d] = ldx<WIDE>(xs + (PAD + dir_off(d, N)));
+                                }
+                                if constexpr (DASH && !(WIDE && LAG > 0)) {
+    #pragma unroll
+                                    for (int d = d0; d < de; ++d) VY[DASH ? d : 0] = ldx<WIDE>(vb + s + (PAD + dir_off(d, N)));
+                                }
                                 float4 Vx[VOX > 0 ? 8 : 1];
                                 if constexpr (VOX > 0) {
-                                    // re-read every step (see below)
+                                    // the voxel terms never change, but they must be re-read every
+                                    // step: hoisting them out of the time loop would hold them in
+                                    // registers, which is what this variant avoids
                                     int vo = PAD + s;
                                     __asm__ volatile("" : "+v"(vo));
-#pragma unroll
+    #pragma unroll
                                     for (int i = 0; i < 8; ++i) Vx[i] = vox4(vv[vo + vox_off(i, N)]);
                                 }
-#pragma unroll
-                                for (int d = 0; d < NDIR; ++d)
-                                    if (d >= d0 && d < d1 && d < d0 + LAG) {
-                                        Q[d] = xs[PAD + dir_off(d, N)];
-                                        if constexpr (DASH) QV[DASH ? d : 0] = vb[s + PAD + dir_off(d, N)];
+                                float cfv[NDIR];
+    #pragma unroll
+                                for (int d = d0; d < de; ++d) {
+                                    if constexpr (WIDE && LAG > 0) {
+                                        if (d + LAG >= de) {
+                                            keep_w(Wk[d]);
+                                            if constexpr (DASH) keep_w(Wv[DASH ? d : 0]);
+                                        }
                                     }
-#pragma unroll
-                                for (int d = 0; d < NDIR; ++d) {
-                                    if (d < d0 || d >= d1) continue;
-                                    const int e = d + LAG < d1 ? d + LAG : d0;
-                                    if (d + LAG < d1) {
-                                        Q[e] = xs[PAD + dir_off(e, N)];
-                                        if constexpr (DASH) QV[DASH ? e : 0] = vb[s + PAD + dir_off(e, N)];
-                                    }
-                                    keep_w(Q[d].w);
-                                    if constexpr (DASH) keep_w(QV[DASH ? d : 0].w);
-                                    const float dx = Q[d].x - xr[k].x, dy = Q[d].y - xr[k].y, dz = Q[d].z - xr[k].z;
+                                    const float dx = Y[d].x - xr[k].x, dy = Y[d].y - xr[k].y, dz = Y[d].z - xr[k].z;
                                     float kk, al, be, cd;
                                     if (from_vox(VOX, d)) {
+                                        // the build's sums, term by term in its order
                                         float4 sm = Vx[VOX > 0 ? vox_idx(d, 0) : 0];
-#pragma unroll
+    #pragma unroll
                                         for (int i = 1; i < vox_cnt(d); ++i) {
                                             const float4 u = Vx[VOX > 0 ? vox_idx(d, i) : 0];
                                             sm.x = add_nf(sm.x, u.x);
@@ -566,162 +798,94 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                     }
                                     float cf;
                                     if constexpr (DASH) {
-                                        const float4 W = QV[DASH ? d : 0];
+                                        const float3 W = VY[DASH ? d : 0];
                                         cf = spring_coef_d<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz),
                                                                   cd,
                                                                   rate(W.x - vr[k].x, W.y - vr[k].y, W.z - vr[k].z, dx, dy, dz));
                                     } else {
                                         cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz));
                                     }
-                                    cs[(d - d0) * CL + PAD] = cf;
+                                    cfv[d] = cf;
                                     Ff[k].x = fmaf(cf, dx, Ff[k].x);
                                     Ff[k].y = fmaf(cf, dy, Ff[k].y);
                                     Ff[k].z = fmaf(cf, dz, Ff[k].z);
                                 }
-                            } else {
-                            float3 Y[NDIR], VY[DASH ? NDIR : 1];
-                            float Wk[NDIR], Wv[DASH ? NDIR : 1];
-                            if constexpr (WIDE && LAG > 0) {
-#pragma unroll
-                                for (int d = d0; d < d1; ++d) {
-                                    const float4 q = xs[PAD + dir_off(d, N)];
-                                    Y[d] = make_float3(q.x, q.y, q.z);
-                                    Wk[d] = q.w;
-                                    if constexpr (DASH) {
-                                        const float4 u = vb[s + PAD + dir_off(d, N)];
-                                        VY[DASH ? d : 0] = make_float3(u.x, u.y, u.z);
-                                        Wv[DASH ? d : 0] = u.w;
-                                    }
-                                    if (d - LAG >= d0) {
-                                        keep_w(Wk[d - LAG >= 0 ? d - LAG : 0]);
-                                        if constexpr (DASH) keep_w(Wv[DASH && d - LAG >= 0 ? d - LAG : 0]);
-                                    }
+    #pragma unroll
+                                for (int d = d0; d < de; ++d) cs[(d - d0) * CL + PAD] = cfv[d];
                                 }
-                            } else {
-#pragma unroll
-                                for (int d = d0; d < d1; ++d) Y[d] = ldx<WIDE>(xs + (PAD + dir_off(d, N)));
-                            }
-                            if constexpr (DASH && !(WIDE && LAG > 0)) {
-#pragma unroll
-                                for (int d = d0; d < d1; ++d) VY[DASH ? d : 0] = ldx<WIDE>(vb + s + (PAD + dir_off(d, N)));
-                            }
-                            float4 Vx[VOX > 0 ? 8 : 1];
-                            if constexpr (VOX > 0) {
-                                // the voxel terms never change, but they must be re-read every
-                                // step: hoisting them out of the time loop would hold them in
-                                // registers, which is what this variant avoids
-                                int vo = PAD + s;
-                                __asm__ volatile("" : "+v"(vo));
-#pragma unroll
-                                for (int i = 0; i < 8; ++i) Vx[i] = vox4(vv[vo + vox_off(i, N)]);
-                            }
-                            float cfv[NDIR];
-#pragma unroll
-                            for (int d = d0; d < d1; ++d) {
-                                if constexpr (WIDE && LAG > 0) {
-                                    if (d + LAG >= d1) {
-                                        keep_w(Wk[d]);
-                                        if constexpr (DASH) keep_w(Wv[DASH ? d : 0]);
-                                    }
-                                }
-                                const float dx = Y[d].x - xr[k].x, dy = Y[d].y - xr[k].y, dz = Y[d].z - xr[k].z;
-                                float kk, al, be, cd;
-                                if (from_vox(VOX, d)) {
-                                    // the build's sums, term by term in its order
-                                    float4 sm = Vx[VOX > 0 ? vox_idx(d, 0) : 0];
-#pragma unroll
-                                    for (int i = 1; i < vox_cnt(d); ++i) {
-                                        const float4 u = Vx[VOX > 0 ? vox_idx(d, i) : 0];
-                                        sm.x = add_nf(sm.x, u.x);
-                                        sm.y = add_nf(sm.y, u.y);
-                                        if (PHASE) sm.z = add_nf(sm.z, u.z);
-                                        if (DASH) sm.w = add_nf(sm.w, u.w);
-                                    }
-                                    kk = sm.x;
-                                    al = mul_nf(sm.y, L0d(c, d));
-                                    be = PHASE ? mul_nf(sm.z, L0d(c, d)) : 0.f;
-                                    cd = sm.w;
-                                } else {
-                                    kk = pk[k][d];
-                                    al = pa[k][d];
-                                    be = PHASE ? pb[k][d] : 0.f;
-                                    cd = DASH ? pd[k][DASH ? d : 0] : 0.f;
-                                }
-                                float cf;
-                                if constexpr (DASH) {
-                                    const float3 W = VY[DASH ? d : 0];
-                                    cf = spring_coef_d<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz),
-                                                              cd,
-                                                              rate(W.x - vr[k].x, W.y - vr[k].y, W.z - vr[k].z, dx, dy, dz));
-                                } else {
-                                    cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz));
-                                }
-                                cfv[d] = cf;
-                                Ff[k].x = fmaf(cf, dx, Ff[k].x);
-                                Ff[k].y = fmaf(cf, dy, Ff[k].y);
-                                Ff[k].z = fmaf(cf, dz, Ff[k].z);
-                            }
-#pragma unroll
-                            for (int d = d0; d < d1; ++d) cs[(d - d0) * CL + PAD] = cfv[d];
-                            }
+                            };
+                            if (CLS && topk[k])
+                                forward(IC<4>{});
+                            else
+                                forward(IC<NDIR>{});
                         }
                         if (FENCE) __builtin_amdgcn_sched_barrier(0);
                     }
                     __syncthreads();
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
-                        const int s = tid + k * BS;
-                        if (s < SL) {
+                        const int s = sk[k];
+                        if (lk[k]) {
                             const float4 *xs = xc + s;
                             const float *cs = coef + s;
-                            float3 Y[NDIR];
-                            float cfv[NDIR], Wk[NDIR];
-                            if constexpr (WIDE && BSWP) {
-                                float4 Q[NDIR];
-#pragma unroll
-                                for (int d = 0; d < NDIR; ++d) {
-                                    if (d < d0 || d >= d1 || d >= d0 + LB) continue;
-                                    Q[d] = xs[PAD - dir_off(d, N)];
+                            // backward springs of directions d0 .. DE - 1: a run in the bottom
+                            // plane has only the four that stay in the plane
+                            auto backward = [&](auto DEC) {
+                                constexpr int DE = decltype(DEC)::value;
+                                const int de = DE < d1 ? DE : d1;
+                                float3 Y[NDIR];
+                                float cfv[NDIR], Wk[NDIR];
+                                if constexpr (WIDE && BSWP) {
+                                    float4 Q[NDIR];
+    #pragma unroll
+                                    for (int d = 0; d < NDIR; ++d) {
+                                        if (d < d0 || d >= de || d >= d0 + LB) continue;
+                                        Q[d] = xs[PAD - dir_off(d, N)];
+                                        cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
+                                    }
+    #pragma unroll
+                                    for (int d = 0; d < NDIR; ++d) {
+                                        if (d < d0 || d >= de) continue;
+                                        const int e = d + LB < de ? d + LB : d0;
+                                        if (d + LB < de) {
+                                            Q[e] = xs[PAD - dir_off(e, N)];
+                                            cfv[e] = cs[(e - d0) * CL + (PAD - dir_off(e, N))];
+                                        }
+                                        keep_w(Q[d].w);
+                                        const float ex = Q[d].x - xr[k].x, ey = Q[d].y - xr[k].y, ez = Q[d].z - xr[k].z;
+                                        Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
+                                        Fb[k].y = fmaf(cfv[d], ey, Fb[k].y);
+                                        Fb[k].z = fmaf(cfv[d], ez, Fb[k].z);
+                                    }
+                                } else {
+    #pragma unroll
+                                for (int d = d0; d < de; ++d) {
+                                    if constexpr (WIDE && LB > 0) {
+                                        const float4 q = xs[PAD - dir_off(d, N)];
+                                        Y[d] = make_float3(q.x, q.y, q.z);
+                                        Wk[d] = q.w;
+                                        if (d - LB >= d0) keep_w(Wk[d - LB >= 0 ? d - LB : 0]);
+                                    } else {
+                                        Y[d] = ldx<WIDE>(xs + (PAD - dir_off(d, N)));
+                                    }
                                     cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
                                 }
-#pragma unroll
-                                for (int d = 0; d < NDIR; ++d) {
-                                    if (d < d0 || d >= d1) continue;
-                                    const int e = d + LB < d1 ? d + LB : d0;
-                                    if (d + LB < d1) {
-                                        Q[e] = xs[PAD - dir_off(e, N)];
-                                        cfv[e] = cs[(e - d0) * CL + (PAD - dir_off(e, N))];
+    #pragma unroll
+                                for (int d = d0; d < de; ++d) {
+                                    if constexpr (WIDE && LB > 0) {
+                                        if (d + LB >= de) keep_w(Wk[d]);
                                     }
-                                    keep_w(Q[d].w);
-                                    const float ex = Q[d].x - xr[k].x, ey = Q[d].y - xr[k].y, ez = Q[d].z - xr[k].z;
+                                    const float ex = Y[d].x - xr[k].x, ey = Y[d].y - xr[k].y, ez = Y[d].z - xr[k].z;
                                     Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
                                     Fb[k].y = fmaf(cfv[d], ey, Fb[k].y);
                                     Fb[k].z = fmaf(cfv[d], ez, Fb[k].z);
                                 }
-                            } else {
-#pragma unroll
-                            for (int d = d0; d < d1; ++d) {
-                                if constexpr (WIDE && LB > 0) {
-                                    const float4 q = xs[PAD - dir_off(d, N)];
-                                    Y[d] = make_float3(q.x, q.y, q.z);
-                                    Wk[d] = q.w;
-                                    if (d - LB >= d0) keep_w(Wk[d - LB >= 0 ? d - LB : 0]);
-                                } else {
-                                    Y[d] = ldx<WIDE>(xs + (PAD - dir_off(d, N)));
                                 }
-                                cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
-                            }
-#pragma unroll
-                            for (int d = d0; d < d1; ++d) {
-                                if constexpr (WIDE && LB > 0) {
-                                    if (d + LB >= d1) keep_w(Wk[d]);
-                                }
-                                const float ex = Y[d].x - xr[k].x, ey = Y[d].y - xr[k].y, ez = Y[d].z - xr[k].z;
-                                Fb[k].x = fmaf(cfv[d], ex, Fb[k].x);
-                                Fb[k].y = fmaf(cfv[d], ey, Fb[k].y);
-                                Fb[k].z = fmaf(cfv[d], ez, Fb[k].z);
-                            }
-                            }
+                            };
+                            if (CLS && botk[k])
+                                backward(IC<4>{});
+                            else
+                                backward(IC<NDIR>{});
                         }
                         if (FENCE) __builtin_amdgcn_sched_barrier(0);
                     }
@@ -733,7 +897,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
             if constexpr ((DASH && VAR == 0) || SBX) __syncthreads();
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
-                const int s = tid + k * BS;
+                const int s = sk[k];
                 if (pres[k]) {
                     float3 vp;
                     if (REC) A.rec_x[(size_t)A.n_steps * base + (size_t)t * SL + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
@@ -749,7 +913,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
         bool mybad = false;
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int s = tid + k * BS;
+            const int s = sk[k];
             if (pres[k]) {
                 A.x[base + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
                 A.v[base + s] = make_float4(vr[k].x, vr[k].y, vr[k].z, 0.f);
@@ -882,7 +1046,9 @@ struct PersistEntry {
 // buffer (one more barrier per step, less LDS); + 256 * LAG pipelined 16-byte
 // neighbour reads; + 4096 * (LB + 1) a separate backward lag; + 131072 / + 262144
 // software-pipelined backward / forward springs; + 2097152 rolled direction
-// loops with every parameter from voxels, + 4194304 * (U - 1) unrolled by U.
+// loops with every parameter from voxels, + 4194304 * (U - 1) unrolled by U;
+// + 524288 the balanced slot plan (top- and bottom-plane runs skip the
+// directions that leave the lattice, runs dealt evenly over the SIMDs).
 // Every entry's LDS arrays must fit one CU's 160 KiB (checked at compile time
 // here, and for the code objects as built by a CPU test, since the compiler may
 // add LDS of its own).
@@ -907,6 +1073,15 @@ constexpr size_t lds_ok() {
         NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072 * BSW + 262144,                              \
             k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, BSW, true>,             \
             k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, BSW, true>,              \
+            lds_ok<lds_bytes<NN + 1, BS, 1>()>()                                                                       \
+    }
+// + 524288: the balanced slot plan with top- and bottom-plane runs skipping
+// the directions that leave the lattice (CLS)
+#define SR_PLSC(NN, BS, F, LF, LB)                                                                         \
+    {                                                                                                        \
+        NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072 + 524288,                                    \
+            k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, true, false, 0, true>,  \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, true, false, 0, true>,   \
             lds_ok<lds_bytes<NN + 1, BS, 1>()>()                                                                       \
     }
 #define SR_PRU(NN, BS, VAR, SBX, F, U)                                                                       \
@@ -956,11 +1131,12 @@ const PersistEntry kPersist[] = {
     // defaults
     SR_PE(1, 64, 1, 0, 1),      SR_PE(2, 64, 1, 0, 1),      SR_PE(3, 64, 1, 0, 1),
     SR_PLF(4, 128, 0, 3, 3, 1), SR_PLF(5, 256, 0, 3, 3, 1), SR_PLF(6, 384, 0, 3, 3, 1), SR_PLF(7, 512, 0, 3, 3, 1),
-    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLS(10, 512, 0, 12, 3),
+    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLSC(10, 512, 0, 12, 3),
     SR_PRU(11, 896, 1, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 3),
     // stored-parameter fallbacks of the voxel-rebuilt defaults, and the next best measured
     SR_PE(11, 256, 1, 0, 1),    SR_PE(12, 768, 2, 0, 1),
-    SR_PLF(10, 448, 0, 3, 3, 1), SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRU(12, 768, 2, 1, 1, 2),
+    SR_PLS(10, 512, 0, 12, 3), SR_PLF(10, 448, 0, 3, 3, 1),
+    SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRU(12, 768, 2, 1, 1, 2),
     // plain one-chunk exchange (cross-check of the pipelined forms) and the recompute variant
     SR_PE(4, 128, 1, 0, 1),     SR_PE(5, 256, 1, 0, 1),     SR_PE(6, 384, 1, 0, 1),     SR_PE(7, 512, 1, 0, 1),
     SR_PE(8, 768, 1, 0, 1),     SR_PE(9, 1024, 1, 0, 1),    SR_PE(10, 512, 1, 0, 1),    SR_PE(10, 704, 0, 0, 1),

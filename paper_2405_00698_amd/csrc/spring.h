@@ -22,15 +22,18 @@ struct Geo {
 // Hooke spring with actuated rest length L(t) = L0 (1 + a sin(w t + phi)):
 // the force on the lower endpoint is k (r - L) d / r = (k - k L / r) d, with
 // d = x_upper - x_lower.  k L = kL0 + kal S + kbe C with (S, C) = (sin, cos)(w t).
-// Returns the scalar coefficient of d.  A collapsed spring (r^2 below 1e-30)
-// has no direction; the guard keeps 1/r finite so an absent spring (all
-// parameters zero) contributes an exact zero.
+// Returns the scalar coefficient of d.  An absent spring (all parameters zero)
+// contributes an exact zero as long as r^2 > 0: every stencil neighbour of a
+// lattice point is another point, an absent lattice point (held far outside
+// the robot, each at its own place) or a ghost slot (farther still), so only
+// a spring collapsed to zero length meets r^2 = 0, and its non-finite force
+// flags the robot as diverged.
 template <bool PHASE>
 __device__ __forceinline__ float spring_coef(float k, float kL0, float kal, float kbe, float S, float C,
                                              float r2) {
     float kL = fmaf(kal, S, kL0);
     if (PHASE) kL = fmaf(kbe, C, kL);
-    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+    const float ir = __builtin_amdgcn_rsqf(r2);
     return fmaf(-kL, ir, k);
 }
 
@@ -43,7 +46,7 @@ __device__ __forceinline__ float spring_coef_d(float k, float kL0, float kal, fl
                                                float kd, float vr) {
     float kL = fmaf(kal, S, kL0);
     if (PHASE) kL = fmaf(kbe, C, kL);
-    const float ir = __builtin_amdgcn_rsqf(fmaxf(r2, 1e-30f));
+    const float ir = __builtin_amdgcn_rsqf(r2);
     return fmaf(kd * vr, ir * ir, fmaf(-kL, ir, k));
 }
 
