@@ -246,9 +246,11 @@ int pop_record(sr_pop *pop, int32_t checkpoint_every, int32_t max_steps);
  * sigmoid weight head, the parallel-sum rule and the MLP in FP32 (the class
  * head, the component step and the topology carry no gradient; with
  * SR_WEIGHT_ACTUATION also through the weight-scaled amplitude and phase);
- * needs the genomes and B (dev) of the build.  Populations with spring or
- * ground dashpots (zeta_spring or zeta_ground != 0) have no adjoint:
- * SR_EUNSUPPORTED.  SR_ESTATE without a recorded run.  Gradients of a
+ * needs the genomes and B (dev) of the build.  With the Table II dashpots
+ * (zeta_spring, zeta_ground) the forces also depend on the velocities: the
+ * recording keeps v_n of every step as well, dJ/dk is taken at fixed dashpot
+ * coefficients, and the genome gradient also flows through c = zeta
+ * sqrt(2 m k_c w).  SR_ESTATE without a recorded run.  Gradients of a
  * diverged robot are undefined. */
 int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, float *g_phi,
                  const float *genomes, const float *B, float *g_genome);

@@ -27,10 +27,12 @@ struct AArgs {
     Planes pl;
     const float4 *x0;
     const float4 *rec_x, *rec_v;  // [n_steps * slot_base + t * slots + s]
+    const float4 *rec_u;          // v_n (dashpots, damped ground), same layout
     int n_steps;
     const float2 *sc;
     float4 *lx, *lv;    // per slot
     float *gk, *gs, *gc;  // per stencil entry
+    float *gd;            // dJ/dc per stencil entry (dashpots)
     SimConst c;
 };
 
@@ -44,9 +46,19 @@ struct AArgs {
 // only (ALAG 0: each read is waited for before the next is issued).
 // ONEBUF (recompute form): one position/adjoint buffer instead of two, with a
 // barrier at the start of each step, so that 12^3 robots fit in LDS.
-template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0, bool ONEBUF = false>
+// DASH (recompute form, one buffer; Table II model): the forces also depend on
+// the velocities v_n of the step.  A spring's dashpot c (v_j - v_i).d^ adds,
+// with d = x_j - x_i, u = lambda_F,j - lambda_F,i, w = (v_j - v_i).d and
+// du = d.u,
+//   lambda_x,i += c/r^2 [du (v_j - v_i) + w u - 2 w du d / r^2]  (minus at j),
+//   lambda_v,i += c du d / r^2                                     (minus at j),
+//   dJ/dc      += -w du / r^2,
+// and the ground force N = k_g(-z) - c_g v_z (where it is not clamped at zero)
+// feeds lambda_z and lambda_vz, with the friction threshold following N.
+template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0, bool ONEBUF = false, bool DASH = false>
 __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     static_assert(ALAG == 0 || XCH, "pipelined reads are for the exchange form");
+    static_assert(!DASH || (!XCH && ONEBUF), "the dashpot adjoint is a one-buffer recompute form");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
@@ -54,6 +66,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     constexpr int NQ = XCH ? 1 : NDIR;
     __shared__ float4 xs[NBUF][XL];
     __shared__ float4 lf[NBUF][XL];
+    __shared__ float4 vs[DASH ? NBUF : 1][DASH ? XL : 1];
     __shared__ float ku[XCH ? 3 * NDIR * CL : 1];
     const int tid = threadIdx.x;
     const SimConst c = A.c;
@@ -75,6 +88,10 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 xs[b][PAD + SL + i] = ghost;
                 lf[b][i] = zero;
                 lf[b][PAD + SL + i] = zero;
+                if constexpr (DASH) {
+                    vs[b][i] = zero;
+                    vs[b][PAD + SL + i] = zero;
+                }
             }
         }
 
@@ -83,6 +100,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         float pk[NPT][NDIR], pa[NPT][NDIR], pb[NPT][NDIR], pik[NPT][NDIR];
         float qk[NPT][NQ], qa[NPT][NQ], qb[NPT][NQ];
         float gk[NPT][NDIR], gs[NPT][NDIR], gc[NPT][NDIR];
+        float pd[NPT][DASH ? NDIR : 1], qd[NPT][DASH ? NQ : 1], gd[NPT][DASH ? NDIR : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int s = tid + k * BS;
@@ -105,6 +123,10 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 gk[k][d] = live ? A.gk[pi] : 0.f;
                 gs[k][d] = live ? A.gs[pi] : 0.f;
                 gc[k][d] = live ? A.gc[pi] : 0.f;
+                if constexpr (DASH) {
+                    pd[k][d] = live ? A.pl.kd[pi] : 0.f;
+                    gd[k][d] = live ? A.gd[pi] : 0.f;
+                }
             }
             if (!XCH) {
 #pragma unroll
@@ -115,6 +137,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     qk[k][d] = ok ? A.pl.k[qi] : 0.f;
                     qa[k][d] = ok ? A.pl.kal[qi] : 0.f;
                     qb[k][d] = (ok && PHASE) ? A.pl.kbe[qi] : 0.f;
+                    if constexpr (DASH) qd[k][d] = ok ? A.pl.kd[qi] : 0.f;
                 }
             }
         }
@@ -122,16 +145,18 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
 
         // the recorded state of each step is read one step ahead, so the global
         // loads are in flight during the previous step's spring part
-        float4 XRn[NPT], VPn[NPT];
+        float4 XRn[NPT], VPn[NPT], VNn[DASH ? NPT : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int s = tid + k * BS;
             if (pres[k] && A.n_steps > 0) {
                 XRn[k] = A.rec_x[rbase + (size_t)(A.n_steps - 1) * SL + s];
                 VPn[k] = A.rec_v[rbase + (size_t)(A.n_steps - 1) * SL + s];
+                if constexpr (DASH) VNn[k] = A.rec_u[rbase + (size_t)(A.n_steps - 1) * SL + s];
             } else {
                 XRn[k] = make_float4(0.f, 0.f, 0.f, 0.f);
                 VPn[k] = XRn[k];
+                if constexpr (DASH) VNn[k] = XRn[k];
             }
         }
         float2 sc_next = A.n_steps > 0 ? A.sc[A.n_steps - 1] : make_float2(0.f, 0.f);
@@ -140,18 +165,20 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
             if (NBUF == 1) __syncthreads();  // the previous step's readers are done with the buffers
             const float2 sct = sc_next;
             if (t > 0) sc_next = A.sc[t - 1];
-            float4 XRc[NPT], VPc[NPT];
+            float4 XRc[NPT], VPc[NPT], VNc[DASH ? NPT : 1];
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int s = tid + k * BS;
                 XRc[k] = XRn[k];
                 VPc[k] = VPn[k];
+                if constexpr (DASH) VNc[k] = VNn[k];
                 if (pres[k] && t > 0) {
                     XRn[k] = A.rec_x[rbase + (size_t)(t - 1) * SL + s];
                     VPn[k] = A.rec_v[rbase + (size_t)(t - 1) * SL + s];
+                    if constexpr (DASH) VNn[k] = A.rec_u[rbase + (size_t)(t - 1) * SL + s];
                 }
             }
-            float3 Xr[NPT], LF[NPT];
+            float3 Xr[NPT], LF[NPT], Vr[DASH ? NPT : 1];
             // node-local part of the reverse step
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
@@ -166,43 +193,83 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     float uy = c.damping * fmaf(c.dt, lx[k].y, lv[k].y);
                     const float uz = c.damping * fmaf(c.dt, lx[k].z, lv[k].z);
                     const bool below = ground && X.z < 0.f;
-                    if (below) {
-                        const float dv = c.mu_kc_dt_m * (-X.z);
-                        const float u = sqrtf(fmaf(VP.y, VP.y, VP.x * VP.x));
-                        if (u <= fmaxf(dv, c.mus_kc_dt_m * (-X.z))) {
-                            ux = 0.f;
-                            uy = 0.f;
-                        } else {
-                            const float hx = VP.x / u, hy = VP.y / u;
-                            const float dot = fmaf(hy, uy, hx * ux);
-                            lx[k].z = fmaf(fz, dot, lx[k].z);
-                            const float cc = dv / u;
-                            const float nx = ux - cc * (ux - hx * dot);
-                            const float ny = uy - cc * (uy - hy * dot);
-                            ux = nx;
-                            uy = ny;
+                    if (DASH && c.gdamp) {
+                        // the damped ground: N = max(k_g (-z) - c_g v_z, 0), the
+                        // friction threshold follows N; the forward's operations
+                        const float4 VN = VNc[DASH ? k : 0];
+                        const float Nf = below ? fmaxf(fmaf(-c.cg, VN.z, c.kc * -X.z), 0.f) : 0.f;
+                        float lN = 0.f;
+                        if (Nf > 0.f) {
+                            const float dv = c.mu_dt_m * Nf;
+                            const float u = sqrtf(fmaf(VP.y, VP.y, VP.x * VP.x));
+                            if (u <= fmaxf(dv, c.mus_dt_m * Nf)) {
+                                ux = 0.f;
+                                uy = 0.f;
+                            } else {
+                                const float hx = VP.x / u, hy = VP.y / u;
+                                const float dot = fmaf(hy, uy, hx * ux);
+                                lN = -c.mu_dt_m * dot;
+                                const float cc = dv / u;
+                                const float nx = ux - cc * (ux - hx * dot);
+                                const float ny = uy - cc * (uy - hy * dot);
+                                ux = nx;
+                                uy = ny;
+                            }
                         }
+                        lF = make_float3(c.dt_m * ux, c.dt_m * uy, c.dt_m * uz);
+                        float lvz = uz;
+                        if (Nf > 0.f) {
+                            lN += lF.z;
+                            lx[k].z = fmaf(-c.kc, lN, lx[k].z);
+                            lvz = fmaf(-c.cg, lN, lvz);
+                        }
+                        lv[k] = make_float3(ux, uy, lvz);
+                    } else {
+                        if (below) {
+                            const float dv = c.mu_kc_dt_m * (-X.z);
+                            const float u = sqrtf(fmaf(VP.y, VP.y, VP.x * VP.x));
+                            if (u <= fmaxf(dv, c.mus_kc_dt_m * (-X.z))) {
+                                ux = 0.f;
+                                uy = 0.f;
+                            } else {
+                                const float hx = VP.x / u, hy = VP.y / u;
+                                const float dot = fmaf(hy, uy, hx * ux);
+                                lx[k].z = fmaf(fz, dot, lx[k].z);
+                                const float cc = dv / u;
+                                const float nx = ux - cc * (ux - hx * dot);
+                                const float ny = uy - cc * (uy - hy * dot);
+                                ux = nx;
+                                uy = ny;
+                            }
+                        }
+                        lv[k] = make_float3(ux, uy, uz);
+                        lF = make_float3(c.dt_m * ux, c.dt_m * uy, c.dt_m * uz);
+                        if (below) lx[k].z = fmaf(-c.kc, lF.z, lx[k].z);
                     }
-                    lv[k] = make_float3(ux, uy, uz);
-                    lF = make_float3(c.dt_m * ux, c.dt_m * uy, c.dt_m * uz);
-                    if (below) lx[k].z = fmaf(-c.kc, lF.z, lx[k].z);
                 }
                 Xr[k] = X;
                 LF[k] = lF;
                 xs[b][PAD + s] = make_float4(X.x, X.y, X.z, 0.f);
                 lf[b][PAD + s] = make_float4(lF.x, lF.y, lF.z, 0.f);
+                if constexpr (DASH) {
+                    const float4 VN = pres[k] ? VNc[DASH ? k : 0] : zero;
+                    Vr[DASH ? k : 0] = make_float3(VN.x, VN.y, VN.z);
+                    vs[DASH ? b : 0][PAD + s] = make_float4(VN.x, VN.y, VN.z, 0.f);
+                }
             }
             __syncthreads();
             // spring part: every node takes K_s (lF_hi - lF_lo) from each spring it touches
-            float3 accs[NPT];
+            float3 accs[NPT], accv[DASH ? NPT : 1];
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 accs[k] = make_float3(0.f, 0.f, 0.f);
+                if constexpr (DASH) accv[DASH ? k : 0] = make_float3(0.f, 0.f, 0.f);
                 const int s = tid + k * BS;
                 if (s >= SL || !pres[k]) continue;
                 const float4 *xsb = xs[b] + s;
                 const float4 *lfb = lf[b] + s;
-                float3 acc = make_float3(0.f, 0.f, 0.f);
+                const float4 *vsb = vs[DASH ? b : 0] + s;
+                float3 acc = make_float3(0.f, 0.f, 0.f), av = make_float3(0.f, 0.f, 0.f);
                 float4 QY[NDIR], QL[NDIR];
                 if constexpr (ALAG > 0) {
 #pragma unroll
@@ -239,7 +306,25 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     const float c1 = fmaf(-kL, ir, pk[k][d]);
                     const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
                     const float c2 = (kL * ir) * ir * ir * du;
-                    const float kx = fmaf(c1, ux, c2 * dx), ky = fmaf(c1, uy, c2 * dy), kz = fmaf(c1, uz, c2 * dz);
+                    float kx = fmaf(c1, ux, c2 * dx), ky = fmaf(c1, uy, c2 * dy), kz = fmaf(c1, uz, c2 * dz);
+                    if constexpr (DASH) {
+                        // dashpot beside the spring (self is the lower end i)
+                        const float3 VJ = ld3(vsb + (PAD + dir_off(d, N)));
+                        const float3 VI = Vr[DASH ? k : 0];
+                        const float wx = VJ.x - VI.x, wy = VJ.y - VI.y, wz = VJ.z - VI.z;
+                        const float cd = pd[k][DASH ? d : 0];
+                        const float ir2 = ir * ir;
+                        const float wv = fmaf(dz, wz, fmaf(dy, wy, dx * wx));
+                        const float ce = cd * ir2, q2 = -2.f * wv * du * ir2;
+                        kx = fmaf(ce, fmaf(du, wx, fmaf(wv, ux, q2 * dx)), kx);
+                        ky = fmaf(ce, fmaf(du, wy, fmaf(wv, uy, q2 * dy)), ky);
+                        kz = fmaf(ce, fmaf(du, wz, fmaf(wv, uz, q2 * dz)), kz);
+                        const float cv = ce * du;
+                        av.x = fmaf(cv, dx, av.x);
+                        av.y = fmaf(cv, dy, av.y);
+                        av.z = fmaf(cv, dz, av.z);
+                        gd[k][DASH ? d : 0] = fmaf(-wv * du, ir2, gd[k][DASH ? d : 0]);
+                    }
                     acc.x += kx;
                     acc.y += ky;
                     acc.z += kz;
@@ -269,12 +354,31 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                         const float c1 = fmaf(-kL, ir, qk[k][d]);
                         const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
                         const float c2 = (kL * ir) * ir * ir * du;
-                        acc.x -= fmaf(c1, ux, c2 * dx);
-                        acc.y -= fmaf(c1, uy, c2 * dy);
-                        acc.z -= fmaf(c1, uz, c2 * dz);
+                        float kx = fmaf(c1, ux, c2 * dx), ky = fmaf(c1, uy, c2 * dy), kz = fmaf(c1, uz, c2 * dz);
+                        if constexpr (DASH) {
+                            // dashpot beside the spring (self is the upper end j)
+                            const float3 VI = ld3(vsb + (PAD - dir_off(d, N)));
+                            const float3 VJ = Vr[DASH ? k : 0];
+                            const float wx = VJ.x - VI.x, wy = VJ.y - VI.y, wz = VJ.z - VI.z;
+                            const float cd = qd[k][DASH ? d : 0];
+                            const float ir2 = ir * ir;
+                            const float wv = fmaf(dz, wz, fmaf(dy, wy, dx * wx));
+                            const float ce = cd * ir2, q2 = -2.f * wv * du * ir2;
+                            kx = fmaf(ce, fmaf(du, wx, fmaf(wv, ux, q2 * dx)), kx);
+                            ky = fmaf(ce, fmaf(du, wy, fmaf(wv, uy, q2 * dy)), ky);
+                            kz = fmaf(ce, fmaf(du, wz, fmaf(wv, uz, q2 * dz)), kz);
+                            const float cv = ce * du;
+                            av.x = fmaf(-cv, dx, av.x);
+                            av.y = fmaf(-cv, dy, av.y);
+                            av.z = fmaf(-cv, dz, av.z);
+                        }
+                        acc.x -= kx;
+                        acc.y -= ky;
+                        acc.z -= kz;
                     }
                 }
                 accs[k] = acc;
+                if constexpr (DASH) accv[DASH ? k : 0] = av;
             }
             if (XCH) {
                 __syncthreads();
@@ -301,6 +405,12 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 lx[k].x += acc.x;
                 lx[k].y += acc.y;
                 lx[k].z += acc.z;
+                if constexpr (DASH) {
+                    const float3 av = accv[DASH ? k : 0];
+                    lv[k].x += av.x;
+                    lv[k].y += av.y;
+                    lv[k].z += av.z;
+                }
             }
         }
         // the adjoint state and the gradient sums carry over to the previous segment
@@ -316,6 +426,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 A.gk[pi] = gk[k][d];
                 A.gs[pi] = gs[k][d];
                 A.gc[pi] = gc[k][d];
+                if constexpr (DASH) A.gd[pi] = gd[k][d];
             }
         }
         __syncthreads();
@@ -325,7 +436,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
 // Terminal adjoint of J = sum_r g_r (1/M_r) sum_i (x_i,x - x0_i,x): lx = g_r / M_r e_x on
 // present nodes, lv = 0, gradient sums zero.
 __global__ void k_adj_init(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const float4 *x0,
-                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc) {
+                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc, float *gd) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= total_slots) return;
     const int r = slot_robot[g];
@@ -340,6 +451,7 @@ __global__ void k_adj_init(const RobotInfo *robots, int total_slots, const int32
         gk[pi] = 0.f;
         gs[pi] = 0.f;
         gc[pi] = 0.f;
+        if (gd) gd[pi] = 0.f;
     }
 }
 
@@ -381,7 +493,9 @@ __global__ void k_adj_springs(const RobotInfo *robots, int total_slots, const in
 // (gk is dJ/dk at fixed a, phi; gs, gc the sums of dJ/dL k sin wt, k cos wt).
 // Voxel v adds k_c w to k and k_c w amp e^{i ph} to Z of each of its 28 springs,
 // with (amp, ph) = (a_c, phi_c), or (w a_c, w phi_c) under weight-scaled
-// actuation, whose w-derivative is k_c a_c (2 w + i w^2 phi_c) e^{i w phi_c}.
+// actuation, whose w-derivative is k_c a_c (2 w + i w^2 phi_c) e^{i w phi_c};
+// and zeta sqrt(2 m k_c w) to the spring's dashpot c, whose w-derivative is
+// zeta sqrt(2 m k_c w) / (2 w).
 struct DwArgs {
     const RobotInfo *robots;
     int total_vox;
@@ -389,10 +503,11 @@ struct DwArgs {
     const uint8_t *kept;
     const float *w;
     Planes pl;
-    const float *gk, *gs, *gc;
+    const float *gk, *gs, *gc, *gd;
     float k_class[5], a_class[5], phi_class[5];
     int weight_act;
     float voxel_len;
+    float dash_c;  // d c / d w of this voxel's dashpot, up to sqrt(k_c / w): zeta sqrt(2 m) / 2
     float *dJdw;
 };
 
@@ -410,6 +525,7 @@ __global__ void k_adj_dw(DwArgs A) {
     const int n = ri.n, N = ri.N;
     const int i = v % n, j = (v / n) % n, kk = v / (n * n);
     const float kc = A.k_class[c], ac = A.a_class[c], pc = A.phi_class[c], wv = A.w[gv];
+    const float dcdw = (A.gd && wv > 0.f) ? A.dash_c * sqrtf(kc / wv) : 0.f;
     float dzr, dzi;  // d(k_c w amp e^{i ph})/dw
     if (A.weight_act) {
         const float cs = cosf(wv * pc), sn = sinf(wv * pc);
@@ -442,6 +558,7 @@ __global__ void k_adj_dw(DwArgs A) {
                 t -= kc * (A.pl.kal[pi] * gs + A.pl.kbe[pi] * gc) * ik * ik;
                 t += L0 * ik * (dzr * gs + dzi * gc);
             }
+            if (A.gd) t = fmaf(dcdw, A.gd[pi], t);
             sum += t;
         }
     }
@@ -608,14 +725,24 @@ struct AdjEntry {
 const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
                          SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AEL(8, 768, 2),
                          SR_AE(9, 1024, false), SR_AE(10, 704, false), SR_AE(11, 1024, false), SR_AE1(12, 1024)};
+// spring dashpots or the damped ground (Table II model): the one-buffer
+// recompute form with the velocity terms
+#define SR_AED(NN, BS) \
+    { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, true, true>, k_adjoint<NN + 1, BS, true, false, 0, true, true> }
+const AdjEntry kAdjD[] = {SR_AED(1, 64),    SR_AED(2, 64),    SR_AED(3, 64),    SR_AED(4, 128),
+                          SR_AED(5, 256),   SR_AED(6, 384),   SR_AED(7, 512),   SR_AED(8, 768),
+                          SR_AED(9, 1024),  SR_AED(10, 1024), SR_AED(11, 1024), SR_AED(12, 1024)};
 
 }  // namespace
 
 hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
-                          const float4 *x0, const float4 *rec_x, const float4 *rec_v, int n_steps, const float2 *sc,
-                          float4 *lx, float4 *lv, float *gk, float *gs, float *gc, SimConst c, hipStream_t st) {
+                          const float4 *x0, const float4 *rec_x, const float4 *rec_v, const float4 *rec_u,
+                          int n_steps, const float2 *sc, float4 *lx, float4 *lv, float *gk, float *gs, float *gc,
+                          float *gd, SimConst c, hipStream_t st) {
+    const bool vel = c.dash || c.gdamp;  // forces that depend on the velocities
+    if (vel && (!rec_u || !gd)) return hipErrorInvalidValue;
     const AdjEntry *e = nullptr;
-    for (const auto &q : kAdj)
+    for (const auto &q : (vel ? kAdjD : kAdj))
         if (q.n == n) e = &q;
     if (!e) return hipErrorInvalidConfiguration;
     AArgs A;
@@ -626,6 +753,7 @@ hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int3
     A.x0 = x0;
     A.rec_x = rec_x;
     A.rec_v = rec_v;
+    A.rec_u = rec_u;
     A.n_steps = n_steps;
     A.sc = sc;
     A.lx = lx;
@@ -633,15 +761,17 @@ hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int3
     A.gk = gk;
     A.gs = gs;
     A.gc = gc;
+    A.gd = gd;
     A.c = c;
     hipLaunchKernelGGL(phase ? e->fn_phase : e->fn, dim3(count), dim3(e->block), 0, st, A);
     return hipGetLastError();
 }
 
 hipError_t launch_adj_init(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const float4 *x0,
-                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc, hipStream_t st) {
+                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc, float *gd,
+                           hipStream_t st) {
     hipLaunchKernelGGL(k_adj_init, dim3((total_slots + 255) / 256), dim3(256), 0, st, robots, total_slots, slot_robot,
-                       x0, dJ, lx, lv, gk, gs, gc);
+                       x0, dJ, lx, lv, gk, gs, gc, gd);
     return hipGetLastError();
 }
 
@@ -655,8 +785,8 @@ hipError_t launch_adj_springs(const RobotInfo *robots, int total_slots, const in
 
 hipError_t launch_adj_genome(const RobotInfo *robots, int R, int total_vox, const int32_t *vox_robot,
                              const uint8_t *kept, const float *w, Planes pl, const float *gk, const float *gs,
-                             const float *gc, const sr_sim_params &p, const float *genomes, const float *B, float *dJdw,
-                             float *g_gen, hipStream_t st) {
+                             const float *gc, const float *gd, const sr_sim_params &p, const float *genomes,
+                             const float *B, float *dJdw, float *g_gen, hipStream_t st) {
     DwArgs A;
     A.robots = robots;
     A.total_vox = total_vox;
@@ -667,6 +797,8 @@ hipError_t launch_adj_genome(const RobotInfo *robots, int R, int total_vox, cons
     A.gk = gk;
     A.gs = gs;
     A.gc = gc;
+    A.gd = p.zeta_spring != 0.f ? gd : nullptr;
+    A.dash_c = (float)(0.5 * (double)p.zeta_spring * sqrt(2.0 * (double)p.mass));
     for (int c = 0; c < 5; ++c) {
         A.k_class[c] = p.k_class[c];
         A.a_class[c] = p.a_class[c];

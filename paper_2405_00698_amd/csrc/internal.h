@@ -116,21 +116,25 @@ hipError_t launch_micro(int which, int iters, int grid, float *out, hipStream_t 
 hipError_t launch_sincos(float2 *sc, const int64_t *d_step, int n, double omega_dt, int on, hipStream_t st);
 hipError_t launch_sincos_at(float2 *sc, int64_t step0, int n, double omega_dt, int on, hipStream_t st);
 
+// recording forward for the adjoint: x_n and the pre-friction velocity v'_n of
+// every step, and (rec_u not null: dashpots or a damped ground) v_n as well
 hipError_t launch_record(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
                          float4 *x, float4 *v, const float2 *sc, int n_steps, uint8_t *diverged, SimConst c,
-                         float4 *rec_x, float4 *rec_v, hipStream_t st);
+                         float4 *rec_x, float4 *rec_v, float4 *rec_u, hipStream_t st);
 hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
-                          const float4 *x0, const float4 *rec_x, const float4 *rec_v, int n_steps, const float2 *sc,
-                          float4 *lx, float4 *lv, float *gk, float *gs, float *gc, SimConst c, hipStream_t st);
+                          const float4 *x0, const float4 *rec_x, const float4 *rec_v, const float4 *rec_u,
+                          int n_steps, const float2 *sc, float4 *lx, float4 *lv, float *gk, float *gs, float *gc,
+                          float *gd, SimConst c, hipStream_t st);
 hipError_t launch_adj_init(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const float4 *x0,
-                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc, hipStream_t st);
+                           const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc, float *gd,
+                           hipStream_t st);
 hipError_t launch_adj_springs(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const int32_t *sid,
                               const int64_t *spring_off, Planes pl, float voxel_len, const float *gk, const float *gs,
                               const float *gc, float *g_k, float *g_a, float *g_phi, hipStream_t st);
 hipError_t launch_adj_genome(const RobotInfo *robots, int R, int total_vox, const int32_t *vox_robot,
                              const uint8_t *kept, const float *w, Planes pl, const float *gk, const float *gs,
-                             const float *gc, const sr_sim_params &p, const float *genomes, const float *B, float *dJdw,
-                             float *g_gen, hipStream_t st);
+                             const float *gc, const float *gd, const sr_sim_params &p, const float *genomes,
+                             const float *B, float *dJdw, float *g_gen, hipStream_t st);
 hipError_t launch_advance(int64_t *d_step, int n, hipStream_t st);
 
 hipError_t launch_plain_step(const RobotInfo *robots, int R, int total_slots, const NodeRow *rows,

@@ -119,9 +119,10 @@ struct sr_pop {
     // segment s is reversed on the population's stream)
     int rec_cap = 0;
     float4 *rec_x[2] = {nullptr, nullptr}, *rec_v[2] = {nullptr, nullptr};
+    float4 *rec_u[2] = {nullptr, nullptr};  // v_n per step (dashpots or a damped ground)
     float4 *tmp_x[2] = {nullptr, nullptr}, *tmp_v[2] = {nullptr, nullptr};
     float4 *lx = nullptr, *lv = nullptr;
-    float *gk = nullptr, *gs = nullptr, *gc = nullptr, *dJdw = nullptr;
+    float *gk = nullptr, *gs = nullptr, *gc = nullptr, *gd = nullptr, *dJdw = nullptr;
     float2 *sc_seg[2] = {nullptr, nullptr};
     hipStream_t adj_st = nullptr;
     hipEvent_t adj_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // start, recorded[2], reversed[2]
@@ -176,7 +177,7 @@ void pop_free(sr_pop *pop) {
                     pop->d_spring_off, pop->q_cls, pop->q_w, pop->vox_robot, pop->ck_x, pop->ck_v,
                     pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
                     pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs,
-                    pop->gc, pop->dJdw, pop->sc_seg[0], pop->sc_seg[1]};
+                    pop->gc, pop->gd, pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto e : pop->adj_ev)
@@ -861,8 +862,6 @@ int pop_record(sr_pop *pop, int32_t checkpoint_every, int32_t max_steps) {
     pop->ck_cap = 0;
     pop->rec_valid = false;
     if (checkpoint_every == 0) return SR_OK;
-    if (pop->p.zeta_spring != 0.f || pop->p.zeta_ground != 0.f)
-        return set_err(SR_EUNSUPPORTED, "no adjoint with spring or ground dashpots");
     const int cap = max_steps / checkpoint_every + 1;
     hipError_t e = dalloc(&pop->ck_x, (size_t)cap * pop->total_slots);
     if (e == hipSuccess) e = dalloc(&pop->ck_v, (size_t)cap * pop->total_slots);
@@ -878,15 +877,19 @@ int ensure_adj_scratch(sr_pop *pop, int K) {
     if (K <= pop->rec_cap) return SR_OK;
     HIPC(pop, hipStreamSynchronize(pop->st));
     void *old[] = {pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
-                   pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs, pop->gc,
-                   pop->dJdw, pop->sc_seg[0], pop->sc_seg[1]};
+                   pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs, pop->gc, pop->gd,
+                   pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1]};
     for (void *p : old)
         if (p) HIPC(pop, hipFree(p));
+    pop->gd = nullptr;
+    pop->rec_u[0] = pop->rec_u[1] = nullptr;
     const size_t S = pop->total_slots;
+    const bool vel = pop->c.dash || pop->c.gdamp;  // the reverse step needs v_n
     hipError_t e = hipSuccess;
     for (int b = 0; b < 2; ++b) {
         if (e == hipSuccess) e = dalloc(&pop->rec_x[b], S * K);
         if (e == hipSuccess) e = dalloc(&pop->rec_v[b], S * K);
+        if (e == hipSuccess && vel) e = dalloc(&pop->rec_u[b], S * K);
         if (e == hipSuccess) e = dalloc(&pop->tmp_x[b], S);
         if (e == hipSuccess) e = dalloc(&pop->tmp_v[b], S);
         if (e == hipSuccess) e = dalloc(&pop->sc_seg[b], (size_t)K);
@@ -896,6 +899,7 @@ int ensure_adj_scratch(sr_pop *pop, int K) {
     if (e == hipSuccess) e = dalloc(&pop->gk, S * NDIR);
     if (e == hipSuccess) e = dalloc(&pop->gs, S * NDIR);
     if (e == hipSuccess) e = dalloc(&pop->gc, S * NDIR);
+    if (e == hipSuccess && vel) e = dalloc(&pop->gd, S * NDIR);
     if (e == hipSuccess) e = dalloc(&pop->dJdw, (size_t)pop->total_vox);
     if (e == hipSuccess && !pop->adj_st) e = hipStreamCreateWithFlags(&pop->adj_st, hipStreamNonBlocking);
     for (auto &ev : pop->adj_ev)
@@ -917,8 +921,6 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     if (!pop->rec_valid || pop->ck_every <= 0)
         return set_err(SR_ESTATE, "no recorded run: call pop_record right after the build, then pop_step");
     if (g_genome && (!genomes || !B)) return set_err(SR_EINVAL, "genome gradient needs the genomes and B");
-    if (pop->p.zeta_spring != 0.f || pop->p.zeta_ground != 0.f)
-        return set_err(SR_EUNSUPPORTED, "no adjoint with spring or ground dashpots");
     const int K = pop->ck_every;
     int rc = ensure_adj_scratch(pop, K);
     if (rc) return rc;
@@ -926,7 +928,7 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     if (rc) return rc;
     const double omega_dt = 2.0 * M_PI * (double)pop->p.act_freq * pop->p.dt;
     HIPC(pop, launch_adj_init(pop->d_robots, pop->total_slots, pop->slot_robot, pop->x0, dJ_dfitness, pop->lx, pop->lv,
-                              pop->gk, pop->gs, pop->gc, pop->st));
+                              pop->gk, pop->gs, pop->gc, pop->gd, pop->st));
     const int64_t T = pop->h_step;
     const int nseg = (int)((T + K - 1) / K);
     // Segments are reversed last to first on the population's stream.  The
@@ -951,7 +953,7 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
         for (const auto &gr : pop->groups)
             HIPC(pop, launch_record(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count, pop->pl,
                                     pop->tmp_x[b], pop->tmp_v[b], pop->sc_seg[b], len, pop->diverged, pop->c,
-                                    pop->rec_x[b], pop->rec_v[b], pop->adj_st));
+                                    pop->rec_x[b], pop->rec_v[b], pop->rec_u[b], pop->adj_st));
         HIPC(pop, hipEventRecord(ev_rec[b], pop->adj_st));
         return SR_OK;
     };
@@ -964,15 +966,16 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
         HIPC(pop, hipStreamWaitEvent(pop->st, ev_rec[b], 0));
         for (const auto &gr : pop->groups)
             HIPC(pop, launch_adjoint(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count, pop->pl,
-                                     pop->x0, pop->rec_x[b], pop->rec_v[b], len, pop->sc_seg[b], pop->lx, pop->lv,
-                                     pop->gk, pop->gs, pop->gc, pop->c, pop->st));
+                                     pop->x0, pop->rec_x[b], pop->rec_v[b], pop->rec_u[b], len, pop->sc_seg[b],
+                                     pop->lx, pop->lv, pop->gk, pop->gs, pop->gc, pop->gd, pop->c, pop->st));
         HIPC(pop, hipEventRecord(ev_rev[b], pop->st));
     }
     HIPC(pop, launch_adj_springs(pop->d_robots, pop->total_slots, pop->slot_robot, pop->sid, pop->d_spring_off, pop->pl,
                                  pop->p.voxel_len, pop->gk, pop->gs, pop->gc, g_k, g_a, g_phi, pop->st));
     if (g_genome)
         HIPC(pop, launch_adj_genome(pop->d_robots, pop->R, pop->total_vox, pop->vox_robot, pop->kept, pop->w, pop->pl,
-                                    pop->gk, pop->gs, pop->gc, pop->p, genomes, B, pop->dJdw, g_genome, pop->st));
+                                    pop->gk, pop->gs, pop->gc, pop->gd, pop->p, genomes, B, pop->dJdw, g_genome,
+                                    pop->st));
     return SR_OK;
 }
 

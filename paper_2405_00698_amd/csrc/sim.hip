@@ -178,8 +178,9 @@ struct PArgs {
     uint8_t *diverged;
     SimConst c;
     // recording form: per step the positions x_n and the pre-friction velocity v'_n
-    // of every slot, at rec_x[n_steps * slot_base + t * slots + s]
-    float4 *rec_x, *rec_v;
+    // of every slot, at rec_x[n_steps * slot_base + t * slots + s]; rec_u (when
+    // not null) the velocity v_n at the start of the step
+    float4 *rec_x, *rec_v, *rec_u;
 };
 
 // Spring parameters rebuilt from voxels (VOX): every spring touching a lattice
@@ -901,6 +902,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 if (pres[k]) {
                     float3 vp;
                     if (REC) A.rec_x[(size_t)A.n_steps * base + (size_t)t * SL + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
+                    if (REC && A.rec_u)
+                        A.rec_u[(size_t)A.n_steps * base + (size_t)t * SL + s] = make_float4(vr[k].x, vr[k].y, vr[k].z, 0.f);
                     integrate_node(c, xr[k], vr[k], Ff[k], Fb[k], REC ? &vp : nullptr);
                     if (REC) A.rec_v[(size_t)A.n_steps * base + (size_t)t * SL + s] = make_float4(vp.x, vp.y, vp.z, 0.f);
                     xn[PAD + s] = make_float4(xr[k].x, xr[k].y, xr[k].z, 1.f);
@@ -1162,6 +1165,18 @@ const PersistEntry kRec[] = {
     SR_RECL(9, 1024, 3, 3, true), SR_RECL(10, 512, 3, 3, true), SR_REC(11, 896, 1),           SR_REC(12, 768, 2),
 };
 
+// recording forms of the spring-dashpot kernels (they carry the phase plane)
+#define SR_RECD(NN, BS, VAR)                                                                               \
+    {                                                                                                       \
+        NN, BS, VAR + 16, k_persist<NN + 1, BS, VAR, false, true, true, true, true>,                        \
+            k_persist<NN + 1, BS, VAR, false, true, true, true, true>, 0                                    \
+    }
+const PersistEntry kRecD[] = {
+    SR_RECD(1, 64, 1),   SR_RECD(2, 64, 1),   SR_RECD(3, 64, 1),   SR_RECD(4, 128, 1),
+    SR_RECD(5, 256, 1),  SR_RECD(6, 384, 1),  SR_RECD(7, 512, 1),  SR_RECD(8, 768, 1),
+    SR_RECD(9, 768, 1),  SR_RECD(10, 512, 1), SR_RECD(11, 512, 2), SR_RECD(12, 512, 0),
+};
+
 const PersistEntry *find_persist(const PersistCfg &cfg) {
     for (const auto &e : kPersist)
         if (e.n == cfg.n && e.block == cfg.block && e.variant == cfg.variant) return &e;
@@ -1220,6 +1235,7 @@ hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo 
     A.c = c;
     A.rec_x = nullptr;
     A.rec_v = nullptr;
+    A.rec_u = nullptr;
     PersistFn fn = phase ? e->fn_phase : e->fn;
     hipLaunchKernelGGL(fn, dim3(grid), dim3(e->block), 0, st, A);
     return hipGetLastError();
@@ -1227,10 +1243,17 @@ hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo 
 
 hipError_t launch_record(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
                          float4 *x, float4 *v, const float2 *sc, int n_steps, uint8_t *diverged, SimConst c,
-                         float4 *rec_x, float4 *rec_v, hipStream_t st) {
+                         float4 *rec_x, float4 *rec_v, float4 *rec_u, hipStream_t st) {
+    // the spring-dashpot model records with the dashpot kernels (the same bits
+    // as its production kernels)
     const PersistEntry *e = nullptr;
-    for (const auto &q : kRec)
-        if (q.n == n) e = &q;
+    if (c.dash) {
+        for (const auto &q : kRecD)
+            if (q.n == n) e = &q;
+    } else {
+        for (const auto &q : kRec)
+            if (q.n == n) e = &q;
+    }
     if (!e) return hipErrorInvalidConfiguration;
     PArgs A;
     A.robots = robots;
@@ -1245,6 +1268,7 @@ hipError_t launch_record(int n, bool phase, const RobotInfo *robots, const int32
     A.c = c;
     A.rec_x = rec_x;
     A.rec_v = rec_v;
+    A.rec_u = rec_u;
     hipLaunchKernelGGL(phase ? e->fn_phase : e->fn, dim3(count), dim3(e->block), 0, st, A);
     return hipGetLastError();
 }

@@ -3,7 +3,8 @@ oracle, through the C ABI: weight-scaled muscle amplitude and phase, spring
 and ground dashpots, static/kinetic friction.  Same bars as the base model:
 spring parameters to FP32 rounding, positions within 1e-3 relative with
 contact, all dashpot kernel configurations bit-identical to the per-step
-kernel, gradients within 1e-2 / 2e-2 relative L2."""
+kernel; gradients, with and without the dampers, against the oracle's
+adjoint at 1e-3 relative L2."""
 import numpy as np
 import pytest
 import torch
@@ -134,12 +135,109 @@ def test_kernel_kind_must_match_model():
     assert (256, 410385) in __import__("paper_2405_00698_amd").api.persist_configs(5)
 
 
-def test_no_adjoint_with_dashpots():
-    sides = [3] * 2
-    cls, w = voxel_population(sides, 66)
-    P = _pop(sides, cls, w)
-    with pytest.raises(SoftRobotError):
-        P.record(10, 100)
+# The Table II model for the adjoint checks: both dampers, weight-scaled
+# muscles, static above kinetic friction; dt 1e-4 s so that 200 steps span
+# 20 ms of contact, as in the base-model checks.
+ADJ = dict(dt=1e-4, mu=0.5, mu_static=0.8, damping=1.0)
+
+
+def _l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _adjoint_vs_oracle(orc, sides, seed, steps, over, label):
+    """Per robot, the worst relative L2 error over (k, a, phi) of the GPU
+    adjoint against the oracle's, with the oracle given the library's own
+    (a, phi) of every spring."""
+    cls, w = voxel_population(sides, seed)
+    P = _pop(sides, cls, w, **over)
+    robots = oracle_robots(orc, sides, cls, w, **_oparams(orc, **over))
+    sp = {k: v.cpu().numpy().astype(np.float64) for k, v in P.springs().items()}
+    M, S, mo, so = P.counts()
+    for r, R in enumerate(robots):
+        R.set_springs(a=sp["a"][so[r]:so[r + 1]], phi=sp["phi"][so[r]:so[r + 1]])
+    P.record(50, steps)
+    P.step(steps)
+    dJ = np.random.default_rng(seed).uniform(0.5, 1.5, size=len(sides)).astype(np.float32)
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in P.backward(torch.from_numpy(dJ).to(DEV)).items()}
+    worst = []
+    for r, R in enumerate(robots):
+        J, gk, ga, gp = R.backward(steps, g=float(dJ[r]))
+        sl = slice(so[r], so[r + 1])
+        l2 = [_l2(g[key][sl], ref) for key, ref in (("k", gk), ("a", ga), ("phi", gp))]
+        say(label, "robot", r, "springs", S[r], "relative L2 (k, a, phi): %.1e %.1e %.1e" % tuple(l2))
+        worst.append(max(l2))
+    return worst
+
+
+@pytest.mark.parametrize("n", [3, 4, 8])
+def test_dashpot_adjoint_matches_oracle(orc, n):
+    """The adjoint through the spring dashpots and the damped ground (the
+    one-buffer recompute kernels with velocity terms) against the oracle's,
+    four robots, 200 steps with contact: the median robot within 1e-3 in
+    relative L2 per group, every robot within 5e-2 (single robots may take the
+    other stick/slip branch at a near-threshold node)."""
+    worst = _adjoint_vs_oracle(orc, [n] * 4, 90 + n, 200, ADJ, "Table II %d^3" % n)
+    say("Table II %d^3: median %.1e, max %.1e" % (n, float(np.median(worst)), max(worst)))
+    assert max(worst) <= 5e-2
+    assert float(np.median(worst)) <= 1e-3
+
+
+def test_ground_damper_adjoint_matches_oracle(orc):
+    """The damped ground alone (no spring dashpots: the forward runs the
+    base-model kernels, the reverse the velocity-aware ones)."""
+    over = dict(ADJ, zeta_spring=0.0, zeta_ground=0.5)
+    worst = _adjoint_vs_oracle(orc, [4] * 4, 95, 200, over, "damped ground 4^3")
+    assert max(worst) <= 5e-2
+    assert float(np.median(worst)) <= 1e-3
+
+
+def test_dashpot_gradients_independent_of_checkpoint_interval():
+    sides = [4] * 4
+    cls, w = voxel_population(sides, 96)
+    dJ = torch.ones(len(sides), device=DEV)
+    ref = None
+    for K in (1, 7, 50, 200):
+        P = _pop(sides, cls, w, **ADJ)
+        P.record(K, 200)
+        P.step(200)
+        g = {k: v.cpu().numpy() for k, v in P.backward(dJ).items()}
+        if ref is None:
+            ref = g
+        for key in ("k", "a", "phi"):
+            assert np.array_equal(g[key], ref[key]), (K, key)
+
+
+def test_dashpot_genome_gradient_matches_oracle(orc):
+    """dJ/dgenome in the full Table II model: through the dashpot
+    coefficient c = zeta sqrt(2 m k_c w) as well as k and the weighted
+    muscles, the sigmoid head and the MLP; robots whose class decisions are
+    clear (oracle margin above 1e-4) within 1e-3 in relative L2."""
+    from paper_2405_00698_amd.api import Population
+    sides = [3] * 6
+    B = inputs.gaussian_B()
+    G = inputs.random_genomes(6, seed=7)
+    steps, K = 150, 50
+    P = Population(sides, params=table2_params(**ADJ))
+    Gt, Bt = torch.from_numpy(G).to(DEV), torch.from_numpy(B).to(DEV)
+    P.build_from_genomes(Gt, Bt, SR_QUERY_FP32)
+    P.record(K, steps)
+    P.step(steps)
+    dJ = np.random.default_rng(8).uniform(0.5, 1.5, size=6).astype(np.float32)
+    gg = P.backward(torch.from_numpy(dJ).to(DEV), genomes=Gt, B=Bt)["genome"].cpu().numpy().astype(np.float64)
+    checked = 0
+    for r in range(6):
+        lg = orc.query(G[r].astype(np.float64), B.astype(np.float64), 3)
+        srt = np.sort(lg[:, :5], axis=1)
+        if (srt[:, -1] - srt[:, -2]).min() <= 1e-4:
+            continue
+        J, go = orc.genome_fitness_grad(G[r].astype(np.float64), B.astype(np.float64), 3, steps,
+                                        **_oparams(orc, **ADJ))
+        e = _l2(gg[r], go * float(dJ[r]))
+        say("robot", r, "genome gradient (Table II model) relative L2 %.2e" % e)
+        assert e <= 1e-3
+        checked += 1
+    assert checked >= 3
 
 
 def test_static_friction_step_and_adjoint(orc):
@@ -163,7 +261,8 @@ def test_static_friction_step_and_adjoint(orc):
         sl = slice(so[r], so[r + 1])
         for key, ref in (("k", gk), ("a", ga)):
             e = float(np.linalg.norm(g[key][sl] - ref) / max(np.linalg.norm(ref), 1e-300))
-            assert e < 1e-2, (r, key, e)
+            say("static friction robot", r, key, "relative L2 %.1e" % e)
+            assert e <= 1e-3, (r, key, e)
 
 
 def test_genome_gradient_weighted_actuation(orc):
@@ -192,7 +291,7 @@ def test_genome_gradient_weighted_actuation(orc):
         go = go * float(dJ[r])
         e = float(np.linalg.norm(gg[r] - go) / max(np.linalg.norm(go), 1e-300))
         say("robot", r, "genome gradient (weighted actuation) relative L2 %.2e" % e)
-        assert e < 2e-2
+        assert e <= 1e-3
         checked += 1
     assert checked >= 3
 
