@@ -420,9 +420,9 @@ def main():
         out["copy_probe_bytes"] = 2 * src.numel() * 4
     if not args.no_extras and args.workload == "uniform":
         peaks = {name: api.microbench(name) for name in ("lds_read_16B", "lds_read_12B", "lds_read_4B",
-                                                         "valu_fma", "valu_rsq")}
-        out["measured_peaks"] = {k: (v / 1e9 if k.startswith("lds") else v / 1e12) for k, v in peaks.items()}
-        out["measured_peaks"]["units"] = "LDS GB/s, VALU T lane-ops/s"
+                                                         "valu_fma", "valu_rsq", "hbm_copy")}
+        out["measured_peaks"] = {k: (v / 1e12 if k.startswith("valu") else v / 1e9) for k, v in peaks.items()}
+        out["measured_peaks"]["units"] = "LDS and HBM GB/s (copy: bytes read plus written), VALU T lane-ops/s"
         out["roofline"]["frac_of_measured_lds_16B"] = lds_gbs / out["measured_peaks"]["lds_read_16B"]
         if lds_moved is not None:
             out["roofline"]["moved_over_algorithmic"] = lds_moved / lds_alg

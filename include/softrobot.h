@@ -159,9 +159,11 @@ int pop_build_from_genomes(sr_pop *pop, const float *genomes, const float *B, in
 int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_per_launch);
 
 /* Roofline microbenchmark on the current device (synchronous): which = 0, 1,
- * 2 LDS reads of 16, 12, 4 bytes per lane; 3 FP32 FMA; 4 v_rsq_f32.  Returns
- * the time of one launch (*seconds) and its work (*units: bytes for LDS
- * reads, lane operations for the VALU cases). */
+ * 2 LDS reads of 16, 12, 4 bytes per lane; 3 FP32 FMA; 4 v_rsq_f32; 5 HBM
+ * streaming copy of 512 MiB (iters passes; allocates its two buffers).
+ * Returns the time of one launch (*seconds) and its work (*units: bytes for
+ * the LDS reads and the copy (read plus written), lane operations for the
+ * VALU cases). */
 int sr_microbench(int32_t which, int32_t iters, double *seconds, double *units);
 
 /* Lists the persistent kernel configurations compiled for side n: writes up

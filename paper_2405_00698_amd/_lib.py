@@ -72,14 +72,18 @@ _SIGS = {
 }
 
 
-def load():
+def load(path=None):
+    """The HIP library with every declared entry point typed (cached).  path:
+    another build of the same library (the tests' poisoned debug build),
+    loaded and returned without replacing the cached one."""
     global _lib
-    if _lib is not None:
+    if path is None and _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError("libsoftrobot.so is not built (run __graft_entry__.build()); "
-                           "there is no fallback path")
-    L = C.CDLL(LIB_PATH)
+    lib_path = LIB_PATH if path is None else path
+    if not os.path.exists(lib_path):
+        raise RuntimeError("%s is not built (run __graft_entry__.build()); "
+                           "there is no fallback path" % os.path.basename(lib_path))
+    L = C.CDLL(lib_path)
     missing = [name for name in _SIGS if not hasattr(L, name)]
     if missing:
         raise RuntimeError("libsoftrobot.so lacks the entry points %s declared in include/softrobot.h; "
@@ -88,7 +92,8 @@ def load():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = res
-    _lib = L
+    if path is None:
+        _lib = L
     return L
 
 

@@ -201,11 +201,13 @@ def persist_configs(n):
     return [(b[i], v[i]) for i in range(cnt)]
 
 
-MICRO = {"lds_read_16B": 0, "lds_read_12B": 1, "lds_read_4B": 2, "valu_fma": 3, "valu_rsq": 4}
+MICRO = {"lds_read_16B": 0, "lds_read_12B": 1, "lds_read_4B": 2, "valu_fma": 3, "valu_rsq": 4, "hbm_copy": 5}
 
 
-def microbench(name, iters=4096):
-    """Measured rate of one roofline microbenchmark: bytes/s (LDS) or lane ops/s (VALU)."""
+def microbench(name, iters=None):
+    """Measured rate of one roofline microbenchmark: bytes/s (LDS, HBM) or lane ops/s (VALU)."""
+    if iters is None:
+        iters = 8 if name == "hbm_copy" else 4096
     sec, units = C.c_double(), C.c_double()
     check(_lib.load().sr_microbench(MICRO[name], int(iters), C.byref(sec), C.byref(units)))
     return units.value / sec.value

@@ -163,6 +163,15 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         for (int t = A.n_steps - 1; t >= 0; --t) {
             const int b = NBUF == 1 ? 0 : (t & 1);
             if (NBUF == 1) __syncthreads();  // the previous step's readers are done with the buffers
+#if SR_POISON_LDS
+            // debug build: each thread's own exchange entries hold NaN until it writes them
+            if (XCH)
+                for (int k = 0; k < NPT; ++k) {
+                    const int s = tid + k * BS;
+                    if (s < SL && pres[k])  // absent slots never write theirs (they stay zero)
+                        for (int q = 0; q < 3 * NDIR; ++q) ku[q * CL + PAD + s] = __builtin_nanf("");
+                }
+#endif
             const float2 sct = sc_next;
             if (t > 0) sc_next = A.sc[t - 1];
             float4 XRc[NPT], VPc[NPT], VNc[DASH ? NPT : 1];

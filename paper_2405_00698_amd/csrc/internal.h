@@ -112,6 +112,8 @@ hipError_t launch_ga(const float *fit, const float *gin, float *gout, int P, int
                      uint64_t pm, float sigma, uint64_t seed, uint64_t gen, int32_t *dec, hipStream_t st);
 
 hipError_t launch_micro(int which, int iters, int grid, float *out, hipStream_t st, double *units);
+hipError_t launch_micro_hbm(const float4 *src, float4 *dst, size_t n, int grid, int passes, hipStream_t st,
+                            double *units);
 
 hipError_t launch_sincos(float2 *sc, const int64_t *d_step, int n, double omega_dt, int on, hipStream_t st);
 hipError_t launch_sincos_at(float2 *sc, int64_t step0, int n, double omega_dt, int on, hipStream_t st);

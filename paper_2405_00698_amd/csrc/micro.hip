@@ -74,7 +74,20 @@ __global__ __launch_bounds__(MB) void k_valu_rsq(float *out, int iters) {
     out[blockIdx.x * MB + threadIdx.x] = s;
 }
 
+// Streaming device copy (16-byte loads and stores, grid-stride): the HBM rate
+// a kernel can reach, read and written bytes together.
+__global__ __launch_bounds__(MB) void k_hbm_copy(const float4 *__restrict__ src, float4 *__restrict__ dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * MB + threadIdx.x; i < n; i += (size_t)gridDim.x * MB) dst[i] = src[i];
+}
+
 }  // namespace
+
+hipError_t launch_micro_hbm(const float4 *src, float4 *dst, size_t n, int grid, int passes, hipStream_t st,
+                            double *units) {
+    for (int p = 0; p < passes; ++p) hipLaunchKernelGGL(k_hbm_copy, dim3(grid), dim3(MB), 0, st, src, dst, n);
+    *units = 2.0 * 16.0 * (double)n * passes;
+    return hipGetLastError();
+}
 
 // which: 0 LDS read 16 B, 1 LDS read 12 B, 2 LDS read 4 B, 3 FP32 FMA, 4 rsq.
 // Returns the work of one launch (bytes or lane operations) in *units.

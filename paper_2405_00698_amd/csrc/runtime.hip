@@ -252,22 +252,31 @@ const char *sr_last_error(void) { return g_err.c_str(); }
 int sr_version(void) { return 1; }
 
 int sr_microbench(int32_t which, int32_t iters, double *seconds, double *units) {
-    if (which < 0 || which > 4 || iters < 1 || !seconds || !units) return set_err(SR_EINVAL, "bad microbenchmark request");
+    if (which < 0 || which > 5 || iters < 1 || !seconds || !units) return set_err(SR_EINVAL, "bad microbenchmark request");
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int grid = (cus > 0 ? cus : 256) * 8;
+    const size_t hbm_n = (size_t)32 << 20;  // 32 Mi float4 = 512 MiB per buffer
     float *out = nullptr;
+    float4 *src = nullptr, *dst = nullptr;
     hipStream_t st = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipMalloc(&out, sizeof(float) * grid * 256);
+    if (e == hipSuccess && which == 5) e = hipMalloc(&src, sizeof(float4) * hbm_n);
+    if (e == hipSuccess && which == 5) e = hipMalloc(&dst, sizeof(float4) * hbm_n);
+    if (e == hipSuccess && which == 5) e = hipMemset(src, 0, sizeof(float4) * hbm_n);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     double u = 0.0;
-    if (e == hipSuccess) e = launch_micro(which, iters, grid, out, st, &u);  // warm-up
+    auto run = [&]() {
+        return which == 5 ? launch_micro_hbm(src, dst, hbm_n, grid * 4, iters, st, &u)
+                          : launch_micro(which, iters, grid, out, st, &u);
+    };
+    if (e == hipSuccess) e = run();  // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, st);
-    if (e == hipSuccess) e = launch_micro(which, iters, grid, out, st, &u);
+    if (e == hipSuccess) e = run();
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -276,6 +285,8 @@ int sr_microbench(int32_t which, int32_t iters, double *seconds, double *units) 
     if (e1) (void)hipEventDestroy(e1);
     if (st) (void)hipStreamDestroy(st);
     if (out) (void)hipFree(out);
+    if (src) (void)hipFree(src);
+    if (dst) (void)hipFree(dst);
     if (e != hipSuccess) return set_err(SR_EHIP, "microbenchmark: %s", hipGetErrorString(e));
     *seconds = ms * 1e-3;
     *units = u;

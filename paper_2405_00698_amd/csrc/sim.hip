@@ -255,7 +255,11 @@ struct IC {
 // upper ends would lie above the lattice), and one wholly in the bottom plane
 // (c = 0) no backward spring of those directions (their lower ends would lie
 // below it), so such runs skip those directions: they are light in the forward
-// phase of a step (top) or in the backward-and-update phase (bottom).  The
+// phase of a step (top) or in the backward-and-update phase (bottom).  A
+// skipped coefficient is that of a spring that does not exist: its entry keeps
+// the zero written when the robot was loaded, which is what the few stencil
+// reads that wrap around the lattice's edge (from slots near the top plane's
+// start) find there.  The
 // runs are dealt to the (slot index k, wave w) places of a workgroup, wave w
 // running on SIMD w mod 4, so that the SIMDs carry equal work in each phase:
 // every light run goes where the larger of the two phase maxima is smallest
@@ -591,6 +595,16 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 for (int ch = 0; ch < NCH; ++ch) {
                     const int d0 = ch * NDC;
                     const int d1 = (ch + 1) * NDC < NDIR ? (ch + 1) * NDC : NDIR;
+                    if constexpr (SR_POISON_LDS) {
+                        // only the entries this phase writes: a top-plane run's skipped
+                        // directions keep the zeros of the robot's start (below)
+#pragma unroll
+                        for (int k = 0; k < NPT; ++k)
+                            if (lk[k]) {
+                                const int dw = (CLS && topk[k]) ? (d1 < 4 ? d1 : 4) : d1;
+                                for (int d = d0; d < dw; ++d) coef[(d - d0) * CL + PAD + sk[k]] = __builtin_nanf("");
+                            }
+                    }
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int s = sk[k];
@@ -653,6 +667,16 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 for (int ch = 0; ch < NCH; ++ch) {
                     const int d0 = ch * NDC;
                     const int d1 = (ch + 1) * NDC < NDIR ? (ch + 1) * NDC : NDIR;
+                    if constexpr (SR_POISON_LDS) {
+                        // only the entries this phase writes: a top-plane run's skipped
+                        // directions keep the zeros of the robot's start (below)
+#pragma unroll
+                        for (int k = 0; k < NPT; ++k)
+                            if (lk[k]) {
+                                const int dw = (CLS && topk[k]) ? (d1 < 4 ? d1 : 4) : d1;
+                                for (int d = d0; d < dw; ++d) coef[(d - d0) * CL + PAD + sk[k]] = __builtin_nanf("");
+                            }
+                    }
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int s = sk[k];

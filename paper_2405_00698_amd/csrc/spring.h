@@ -5,6 +5,15 @@
 
 #include "internal.h"
 
+// Debug build (SR_POISON_LDS = 1): at the start of each exchange phase every
+// thread fills its own slots' exchange entries in LDS with NaN before it
+// writes them, so an entry read without having been written in that phase (a
+// missing barrier, a skipped direction that is read after all) shows up as a
+// NaN in the results.  Product builds compile it out.
+#ifndef SR_POISON_LDS
+#define SR_POISON_LDS 0
+#endif
+
 namespace sr {
 
 // Dense lattice of a robot with side n (N = n + 1 points per side) as held in

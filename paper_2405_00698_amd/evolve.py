@@ -61,23 +61,33 @@ def rule_supervisor(history):
 
 def evolve(sides, generations=100, sim_steps=10000, seed_genome=1, seed_ga=3, sigma_B=1.0,
            params=None, supervisor=None, empty_bias=None, log=None, precision=SR_QUERY_BF16,
-           sim_params=None, **sim):
+           sim_params=None, start_generation=0, genomes=None, out_genomes=None, **sim):
     """Runs `generations` generations on the given grid sides; returns the
     per-generation history (parameters, fitness statistics, diversity, times).
     sim_params: a full sr_sim_params (e.g. table2_params()); else the defaults
-    with the keyword overrides in **sim."""
+    with the keyword overrides in **sim.
+    Resuming: `genomes` ([R, 8710], host or device) replaces the seeded
+    initial genomes and `start_generation` numbers the first generation run
+    (the GA draws depend only on (seed_ga, generation, child)), so a run
+    stopped after generation g - 1 and resumed with its genomes at g repeats
+    the uninterrupted run bit for bit.  out_genomes (device [R, 8710]) receives
+    the genomes the last generation bred."""
     dev = torch.device("cuda:0")
     R = len(sides)
     params = dict(elite_frac=0.3, tournament_k=4, p_cross=0.4, p_mut=0.1, sigma=0.02) if params is None else params
     B = torch.from_numpy(inputs.gaussian_B(sigma=sigma_B)).to(dev)
-    G = [torch.from_numpy(inputs.random_genomes(R, seed=seed_genome, empty_bias=empty_bias)).to(dev),
-         torch.empty((R, inputs.GENOME_LEN), dtype=torch.float32, device=dev)]
+    if genomes is None:
+        g0 = torch.from_numpy(inputs.random_genomes(R, seed=seed_genome, empty_bias=empty_bias)).to(dev)
+    else:
+        g0 = torch.as_tensor(genomes, dtype=torch.float32).to(dev).clone()
+    G = [g0, torch.empty((R, inputs.GENOME_LEN), dtype=torch.float32, device=dev)]
     P = Population(sides, params=sim_params, **sim)
     fit = torch.empty(R, dtype=torch.float32, device=dev)
     history = []
-    for g in range(generations):
+    for i in range(generations):
+        g = start_generation + i
         t0 = time.perf_counter()
-        cur, nxt = G[g % 2], G[(g + 1) % 2]
+        cur, nxt = G[i % 2], G[(i + 1) % 2]
         P.build_from_genomes(cur, B, precision)
         P.step(sim_steps)
         P.fitness(fit)
@@ -99,6 +109,8 @@ def evolve(sides, generations=100, sim_steps=10000, seed_genome=1, seed_ga=3, si
         if log is not None:
             log.write(json.dumps(rec) + "\n")
             log.flush()
+    if out_genomes is not None and generations > 0:
+        out_genomes.copy_(G[generations % 2])
     P.close()
     return history
 

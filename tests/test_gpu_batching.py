@@ -110,3 +110,25 @@ def test_codesign_driver_table2_model_and_sigma_sweep():
         best = [r["fit_max"] for r in runs[0]]
         assert all(np.isfinite(best)) and all(b2 >= b1 for b1, b2 in zip(best, best[1:]))
         say("sigma_B", s, "best", ["%.5f" % b for b in best], "diversity %.3f" % runs[0][-1]["div_morph"])
+
+
+def test_codesign_loop_resumes_at_a_generation_bitwise():
+    """A run stopped after generation g - 1 and resumed from its genomes at
+    generation g repeats generations g..G of the uninterrupted run bit for bit
+    (the GA draws depend only on (seed, generation, child)); two resume points,
+    an uneven population."""
+    from paper_2405_00698_amd.evolve import evolve
+    sides = [4, 5, 6, 4, 7, 5, 6, 8, 4, 5, 6, 4, 7, 5, 6, 8]
+    R, G, steps = len(sides), 6, 400
+    full = torch.empty((R, inputs.GENOME_LEN), device=DEV)
+    h_full = evolve(sides, generations=G, sim_steps=steps, out_genomes=full)
+    for g in (2, 4):
+        mid = torch.empty((R, inputs.GENOME_LEN), device=DEV)
+        h_a = evolve(sides, generations=g, sim_steps=steps, out_genomes=mid)
+        end = torch.empty((R, inputs.GENOME_LEN), device=DEV)
+        h_b = evolve(sides, generations=G - g, sim_steps=steps, start_generation=g, genomes=mid, out_genomes=end)
+        assert [r["generation"] for r in h_b] == list(range(g, G))
+        for key in ("fit_max", "fit_mean", "fit_min", "div_morph", "div_genome"):
+            assert [r[key] for r in h_a + h_b] == [r[key] for r in h_full], (g, key)
+        assert torch.equal(end, full), g
+    say("resume: best fitness per generation", ["%.4f" % r["fit_max"] for r in h_full])
