@@ -409,7 +409,9 @@ template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool
           int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false,
           int ROLL = 0, bool CLS = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
-    static_assert(!CLS || (VAR == 1 && ROLL == 0), "the balanced slot plan is a form of the one-chunk exchange");
+    static_assert(!CLS || VAR == 1 || ROLL > 0,
+                  "the balanced slot plan skips directions in the one-chunk or the rolled exchange");
+    static_assert(!CLS || VAR == 0 || (NDIR + VAR - 1) / VAR >= 4, "the first chunk holds the in-plane directions");
     static_assert(ROLL == 0 || (VAR >= 1 && VOX == 2 && !DASH && !REC && WIDE && LAG == 0 && !FSWP && !BSWP),
                   "the rolled direction loop is a form of the exchange with every parameter from voxels");
     static_assert(!FSWP || (WIDE && VAR == 1 && LAG > 0),
@@ -451,8 +453,9 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 const int u = plan.unit[k][w];
                 sk[k] = 64 * u + (tid & 63);
                 lk[k] = u >= 0 && sk[k] < SL;
-                topk[k] = u >= 0 && run_class<N>(u) == RUN_TOP;
-                botk[k] = u >= 0 && run_class<N>(u) == RUN_BOTTOM;
+                // wave-uniform (scalar) so that branches and loop bounds on them stay scalar
+                topk[k] = __builtin_amdgcn_readfirstlane(u >= 0 && run_class<N>(u) == RUN_TOP ? 1 : 0) != 0;
+                botk[k] = __builtin_amdgcn_readfirstlane(u >= 0 && run_class<N>(u) == RUN_BOTTOM ? 1 : 0) != 0;
             } else {
                 sk[k] = tid + k * BS;
                 lk[k] = sk[k] < SL;
@@ -592,6 +595,10 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 // Rolled form: one direction per iteration and nothing indexed by
                 // it but LDS addresses, so no per-direction arrays go to scratch.
                 // The operations and their order are those of the unrolled form.
+                // The chunk loop unrolls, so each direction loop has a constant
+                // trip count (a runtime one would stay rolled: its body holds
+                // inline asm, which the unroller will not give a remainder loop).
+#pragma unroll
                 for (int ch = 0; ch < NCH; ++ch) {
                     const int d0 = ch * NDC;
                     const int d1 = (ch + 1) * NDC < NDIR ? (ch + 1) * NDC : NDIR;
@@ -613,8 +620,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                             float *cs = coef + s;
                             int vo = PAD + s;
                             __asm__ volatile("" : "+v"(vo));
-#pragma unroll ROLL
-                            for (int d = d0; d < d1; ++d) {
+                            auto fwd = [&](int d) {
                                 const float4 q = xs[PAD + rdir_off(d, N)];
                                 keep_w(q.w);
                                 const float dx = q.x - xr[k].x, dy = q.y - xr[k].y, dz = q.z - xr[k].z;
@@ -636,6 +642,17 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                 Ff[k].x = fmaf(cf, dx, Ff[k].x);
                                 Ff[k].y = fmaf(cf, dy, Ff[k].y);
                                 Ff[k].z = fmaf(cf, dz, Ff[k].z);
+                            };
+                            // a top-plane run has only the four in-plane directions, all in
+                            // the first chunk (constant trip count, so the loop unrolls)
+                            if (CLS && topk[k]) {
+                                if (ch == 0) {
+#pragma unroll ROLL
+                                    for (int d = 0; d < 4; ++d) fwd(d);
+                                }
+                            } else {
+#pragma unroll ROLL
+                                for (int d = d0; d < d1; ++d) fwd(d);
                             }
                         }
                         if (FENCE) __builtin_amdgcn_sched_barrier(0);
@@ -647,8 +664,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         if (lk[k]) {
                             const float4 *xs = xc + s;
                             const float *cs = coef + s;
-#pragma unroll ROLL
-                            for (int d = d0; d < d1; ++d) {
+                            auto bwd = [&](int d) {
                                 const float4 q = xs[PAD - rdir_off(d, N)];
                                 const float cf = cs[(d - d0) * CL + (PAD - rdir_off(d, N))];
                                 keep_w(q.w);
@@ -656,6 +672,16 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                 Fb[k].x = fmaf(cf, ex, Fb[k].x);
                                 Fb[k].y = fmaf(cf, ey, Fb[k].y);
                                 Fb[k].z = fmaf(cf, ez, Fb[k].z);
+                            };
+                            // a bottom-plane run has only the four in-plane directions
+                            if (CLS && botk[k]) {
+                                if (ch == 0) {
+#pragma unroll ROLL
+                                    for (int d = 0; d < 4; ++d) bwd(d);
+                                }
+                            } else {
+#pragma unroll ROLL
+                                for (int d = d0; d < d1; ++d) bwd(d);
                             }
                         }
                         if (FENCE) __builtin_amdgcn_sched_barrier(0);
@@ -1118,6 +1144,13 @@ constexpr size_t lds_ok() {
             k_persist<NN + 1, BS, VAR, F, true, false, true, false, 2, SBX, 0, -1, false, false, U>,         \
             lds_ok<lds_bytes<NN + 1, BS, VAR, false, 2, SBX>()>()                                                      \
     }
+#define SR_PRUC(NN, BS, VAR, SBX, F, U)                                                                      \
+    {                                                                                                        \
+        NN, BS, VAR + 4 * F + 64 + 128 * SBX + 2097152 + 4194304 * (U - 1) + 524288,                         \
+            k_persist<NN + 1, BS, VAR, F, false, false, true, false, 2, SBX, 0, -1, false, false, U, true>,  \
+            k_persist<NN + 1, BS, VAR, F, true, false, true, false, 2, SBX, 0, -1, false, false, U, true>,   \
+            lds_ok<lds_bytes<NN + 1, BS, VAR, false, 2, SBX>()>()                                                      \
+    }
 #define SR_PVL(NN, BS, VAR, VOX, SBX, F, LG)                                                              \
     {                                                                                                        \
         NN, BS, VAR + 4 * F + 32 * VOX + 128 * SBX + 256 * LG,                                               \
@@ -1159,11 +1192,11 @@ const PersistEntry kPersist[] = {
     SR_PE(1, 64, 1, 0, 1),      SR_PE(2, 64, 1, 0, 1),      SR_PE(3, 64, 1, 0, 1),
     SR_PLF(4, 128, 0, 3, 3, 1), SR_PLF(5, 256, 0, 3, 3, 1), SR_PLF(6, 384, 0, 3, 3, 1), SR_PLF(7, 512, 0, 3, 3, 1),
     SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLSC(10, 512, 0, 12, 3),
-    SR_PRU(11, 896, 1, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 3),
+    SR_PRUC(11, 896, 1, 1, 1, 3), SR_PRUC(12, 768, 2, 1, 1, 3),
     // stored-parameter fallbacks of the voxel-rebuilt defaults, and the next best measured
     SR_PE(11, 256, 1, 0, 1),    SR_PE(12, 768, 2, 0, 1),
     SR_PLS(10, 512, 0, 12, 3), SR_PLF(10, 448, 0, 3, 3, 1),
-    SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRU(12, 768, 2, 1, 1, 2),
+    SR_PRU(11, 896, 1, 1, 1, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRU(12, 768, 2, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 2),
     // plain one-chunk exchange (cross-check of the pipelined forms) and the recompute variant
     SR_PE(4, 128, 1, 0, 1),     SR_PE(5, 256, 1, 0, 1),     SR_PE(6, 384, 1, 0, 1),     SR_PE(7, 512, 1, 0, 1),
     SR_PE(8, 768, 1, 0, 1),     SR_PE(9, 1024, 1, 0, 1),    SR_PE(10, 512, 1, 0, 1),    SR_PE(10, 704, 0, 0, 1),
