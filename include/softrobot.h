@@ -190,7 +190,13 @@ int pop_set_graphs(sr_pop *pop, int32_t enable);
  *     position buffer;
  *   +256 * L keeps up to L + 1 neighbour reads in flight (L < 16);
  *   +4096 * (B + 1) sets the backward springs' reads apart (B in flight);
- *   +131072 / +262144 software-pipeline the backward / forward springs.
+ *   +131072 / +262144 software-pipeline the backward / forward springs;
+ *   +524288 cuts the slots into runs of 64, one wave each, so that runs in
+ *     the top / bottom lattice plane skip the directions leaving the lattice;
+ *   +1048576 pads each coefficient row only by its own stencil offset (less
+ *     LDS, for the one-chunk exchange at the largest sides);
+ *   +2097152 + 4194304 * (U - 1) leaves the direction loops rolled (unrolled
+ *     by U), with every parameter rebuilt from voxels.
  * sr_persist_configs lists the compiled combinations.  All variants of one
  * kind give bit-identical results.  SR_EUNSUPPORTED for a combination the
  * library lacks or that does not match the population's physics. */

@@ -205,12 +205,39 @@ __device__ __forceinline__ float mul_nf(float a, float b) {
     return a * b;
 }
 
-template <int N, int BS, int VAR, bool DASH = false, int VOX = 0, bool SBX = false>
+// Coefficient rows.  Uniform rows (one per direction of a chunk, CL entries
+// each): slot s stores chunk-local direction j at j CL + PAD + s, and the
+// backward read of slot s at s - off(d) stays inside the row's PAD leading
+// zeros.  Tight rows (one chunk only): row d is preceded by just off(d) zeros,
+// 13 SL + sum of off(d) entries in all, which lets the one-chunk exchange of
+// the 12^3 lattice (13^3 points) fit in LDS beside one position buffer.
+template <int N>
+__host__ __device__ constexpr int tight_row(int d) {
+    int r = 0;
+    for (int e = 0; e < d; ++e) r += N * N * N + dir_off(e, N);
+    return r;
+}
+// + s: where slot s stores its forward coefficient of direction d
+template <int N, bool TCR>
+__host__ __device__ constexpr int coef_w(int d, int d0) {
+    return TCR ? tight_row<N>(d) + dir_off(d, N) : (d - d0) * Geo<N>::CL + Geo<N>::PAD;
+}
+// + s: where slot s reads the coefficient of its backward spring of direction d
+template <int N, bool TCR>
+__host__ __device__ constexpr int coef_r(int d, int d0) {
+    return TCR ? tight_row<N>(d) : (d - d0) * Geo<N>::CL + Geo<N>::PAD - dir_off(d, N);
+}
+template <int N, int NDC, bool TCR>
+__host__ __device__ constexpr int coef_len() {
+    return TCR ? tight_row<N>(NDIR) : NDC * Geo<N>::CL;
+}
+
+template <int N, int BS, int VAR, bool DASH = false, int VOX = 0, bool SBX = false, bool TCR = false>
 constexpr size_t lds_bytes() {
     using G = Geo<N>;
     constexpr int NDC = VAR == 0 ? 0 : (NDIR + VAR - 1) / VAR;
-    return ((SBX ? 1 : 2) + (DASH ? 1 : 0)) * sizeof(float4) * G::XL + sizeof(float) * NDC * G::CL +
-           (VOX ? sizeof(float4) * G::CL : 0);
+    return ((SBX ? 1 : 2) + (DASH ? 1 : 0)) * sizeof(float4) * G::XL +
+           sizeof(float) * (NDC > 0 ? coef_len<N, NDC, TCR>() : 0) + (VOX ? sizeof(float4) * G::CL : 0);
 }
 
 // Direction geometry as plain arithmetic, for loops over a run-time (wave-
@@ -394,6 +421,9 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 //   ROLL   0: direction loops fully unrolled; U > 0: left rolled and unrolled
 //          by U, with no per-direction arrays: each iteration reads, computes
 //          and stores one direction (offsets are wave-uniform)
+//   CLS    the balanced slot plan: runs of 64 slots, top- and bottom-plane runs
+//          skip the directions that leave the lattice
+//   TCR    tight coefficient rows (one-chunk exchange, above)
 //
 // LAG (exchange variants, 16-byte reads): the neighbour reads of a slot are
 // issued back to back with at most LAG + 1 outstanding; the read LAG places
@@ -407,8 +437,9 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 // coefficient as soon as it is computed).
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
           int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false,
-          int ROLL = 0, bool CLS = false>
+          int ROLL = 0, bool CLS = false, bool TCR = false>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    static_assert(!TCR || (VAR == 1 && ROLL == 0), "tight coefficient rows hold one chunk of unrolled directions");
     static_assert(!CLS || VAR == 1 || ROLL > 0,
                   "the balanced slot plan skips directions in the one-chunk or the rolled exchange");
     static_assert(!CLS || VAR == 0 || (NDIR + VAR - 1) / VAR >= 4, "the first chunk holds the in-plane directions");
@@ -431,7 +462,8 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
     // never alias position loads and can keep many loads in flight
     __shared__ float4 xb0[XL];
     __shared__ float4 xb1[SBX ? 1 : XL];
-    __shared__ float coef[NDC > 0 ? NDC * CL : 1];
+    constexpr int CLEN = NDC > 0 ? coef_len<N, NDC, TCR>() : 1;
+    __shared__ float coef[CLEN];
     __shared__ float4 vb[DASH ? XL : 1];
     typedef typename VoxT<PHASE || DASH>::T VT;
     __shared__ VT vv[VOX ? CL : 1];
@@ -473,7 +505,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
         const float lim = c.lim * (N - 1);
 
         if (VAR != 0)
-            for (int i = tid; i < NDC * CL; i += BS) coef[i] = 0.f;
+            for (int i = tid; i < CLEN; i += BS) coef[i] = 0.f;
         const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f);
         for (int i = tid; i < PAD; i += BS) {
             xb0[i] = ghost;
@@ -700,7 +732,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         for (int k = 0; k < NPT; ++k)
                             if (lk[k]) {
                                 const int dw = (CLS && topk[k]) ? (d1 < 4 ? d1 : 4) : d1;
-                                for (int d = d0; d < dw; ++d) coef[(d - d0) * CL + PAD + sk[k]] = __builtin_nanf("");
+                                for (int d = d0; d < dw; ++d) coef[coef_w<N, TCR>(d, d0) + sk[k]] = __builtin_nanf("");
                             }
                     }
 #pragma unroll
@@ -773,7 +805,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                         } else {
                                             cf = spring_coef<PHASE>(kk, kk * L0d(c, d), al, be, sct.x, sct.y, len2(dx, dy, dz));
                                         }
-                                        cs[(d - d0) * CL + PAD] = cf;
+                                        cs[coef_w<N, TCR>(d, d0)] = cf;
                                         Ff[k].x = fmaf(cf, dx, Ff[k].x);
                                         Ff[k].y = fmaf(cf, dy, Ff[k].y);
                                         Ff[k].z = fmaf(cf, dz, Ff[k].z);
@@ -862,7 +894,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                     Ff[k].z = fmaf(cf, dz, Ff[k].z);
                                 }
     #pragma unroll
-                                for (int d = d0; d < de; ++d) cs[(d - d0) * CL + PAD] = cfv[d];
+                                for (int d = d0; d < de; ++d) cs[coef_w<N, TCR>(d, d0)] = cfv[d];
                                 }
                             };
                             if (CLS && topk[k])
@@ -892,7 +924,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                     for (int d = 0; d < NDIR; ++d) {
                                         if (d < d0 || d >= de || d >= d0 + LB) continue;
                                         Q[d] = xs[PAD - dir_off(d, N)];
-                                        cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
+                                        cfv[d] = cs[coef_r<N, TCR>(d, d0)];
                                     }
     #pragma unroll
                                     for (int d = 0; d < NDIR; ++d) {
@@ -900,7 +932,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                         const int e = d + LB < de ? d + LB : d0;
                                         if (d + LB < de) {
                                             Q[e] = xs[PAD - dir_off(e, N)];
-                                            cfv[e] = cs[(e - d0) * CL + (PAD - dir_off(e, N))];
+                                            cfv[e] = cs[coef_r<N, TCR>(e, d0)];
                                         }
                                         keep_w(Q[d].w);
                                         const float ex = Q[d].x - xr[k].x, ey = Q[d].y - xr[k].y, ez = Q[d].z - xr[k].z;
@@ -919,7 +951,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                                     } else {
                                         Y[d] = ldx<WIDE>(xs + (PAD - dir_off(d, N)));
                                     }
-                                    cfv[d] = cs[(d - d0) * CL + (PAD - dir_off(d, N))];
+                                    cfv[d] = cs[coef_r<N, TCR>(d, d0)];
                                 }
     #pragma unroll
                                 for (int d = d0; d < de; ++d) {
@@ -1101,7 +1133,8 @@ struct PersistEntry {
 // software-pipelined backward / forward springs; + 2097152 rolled direction
 // loops with every parameter from voxels, + 4194304 * (U - 1) unrolled by U;
 // + 524288 the balanced slot plan (top- and bottom-plane runs skip the
-// directions that leave the lattice, runs dealt evenly over the SIMDs).
+// directions that leave the lattice, runs dealt evenly over the SIMDs);
+// + 1048576 tight coefficient rows.
 // Every entry's LDS arrays must fit one CU's 160 KiB (checked at compile time
 // here, and for the code objects as built by a CPU test, since the compiler may
 // add LDS of its own).
@@ -1137,12 +1170,15 @@ constexpr size_t lds_ok() {
             k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, true, false, 0, true>,   \
             lds_ok<lds_bytes<NN + 1, BS, 1>()>()                                                                       \
     }
-#define SR_PRU(NN, BS, VAR, SBX, F, U)                                                                       \
+// + 1048576: tight coefficient rows (with the balanced slot plan, software-
+// pipelined backward springs, optionally pipelined forward ones and one
+// position buffer)
+#define SR_PLT(NN, BS, F, LF, LB, SBX, FSW)                                                                 \
     {                                                                                                        \
-        NN, BS, VAR + 4 * F + 64 + 128 * SBX + 2097152 + 4194304 * (U - 1),                                  \
-            k_persist<NN + 1, BS, VAR, F, false, false, true, false, 2, SBX, 0, -1, false, false, U>,        \
-            k_persist<NN + 1, BS, VAR, F, true, false, true, false, 2, SBX, 0, -1, false, false, U>,         \
-            lds_ok<lds_bytes<NN + 1, BS, VAR, false, 2, SBX>()>()                                                      \
+        NN, BS, 1 + 4 * F + 128 * SBX + 256 * LF + 4096 * (LB + 1) + 131072 + 262144 * FSW + 524288 + 1048576, \
+            k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, SBX, LF, LB, true, FSW, 0, true, true>,  \
+            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, SBX, LF, LB, true, FSW, 0, true, true>,   \
+            lds_ok<lds_bytes<NN + 1, BS, 1, false, 0, SBX, true>()>()                                                  \
     }
 #define SR_PRUC(NN, BS, VAR, SBX, F, U)                                                                      \
     {                                                                                                        \
@@ -1192,11 +1228,11 @@ const PersistEntry kPersist[] = {
     SR_PE(1, 64, 1, 0, 1),      SR_PE(2, 64, 1, 0, 1),      SR_PE(3, 64, 1, 0, 1),
     SR_PLF(4, 128, 0, 3, 3, 1), SR_PLF(5, 256, 0, 3, 3, 1), SR_PLF(6, 384, 0, 3, 3, 1), SR_PLF(7, 512, 0, 3, 3, 1),
     SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLSC(10, 512, 0, 12, 3),
-    SR_PRUC(11, 896, 1, 1, 1, 3), SR_PRUC(12, 768, 2, 1, 1, 3),
-    // stored-parameter fallbacks of the voxel-rebuilt defaults, and the next best measured
-    SR_PE(11, 256, 1, 0, 1),    SR_PE(12, 768, 2, 0, 1),
+    SR_PLT(11, 896, 0, 2, 2, 0, 1), SR_PLT(12, 768, 0, 3, 2, 1, 1),
+    // the next best measured
+    SR_PLT(11, 896, 0, 3, 3, 0, 1), SR_PLT(12, 768, 0, 2, 2, 1, 1),
     SR_PLS(10, 512, 0, 12, 3), SR_PLF(10, 448, 0, 3, 3, 1),
-    SR_PRU(11, 896, 1, 1, 1, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRU(12, 768, 2, 1, 1, 3), SR_PRU(12, 768, 2, 1, 1, 2),
+    SR_PRUC(11, 896, 1, 1, 1, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRUC(12, 768, 2, 1, 1, 3),
     // plain one-chunk exchange (cross-check of the pipelined forms) and the recompute variant
     SR_PE(4, 128, 1, 0, 1),     SR_PE(5, 256, 1, 0, 1),     SR_PE(6, 384, 1, 0, 1),     SR_PE(7, 512, 1, 0, 1),
     SR_PE(8, 768, 1, 0, 1),     SR_PE(9, 1024, 1, 0, 1),    SR_PE(10, 512, 1, 0, 1),    SR_PE(10, 704, 0, 0, 1),
