@@ -75,15 +75,23 @@ __global__ __launch_bounds__(QB) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 }
 
 // ---------------------------------------------------------------- BF16 MFMA form
-// Activations are kept transposed (features x voxels) so that each layer is
-// D = W * H^T with the weights as the MFMA A operand and the activations as B:
-// with v_mfma_f32_16x16x16 (A: lane l holds row l%16, k = 4(l/16)..+3; B: lane l
-// holds column l%16, the same k; D: lane l holds column l%16, rows 4(l/16)..+3)
-// the D fragment of output block m is exactly the B fragment of input block m of
-// the next layer, so activations never leave registers.  One wave handles 16
-// voxels; weights are staged in LDS as BF16 (round to nearest even).
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+// Activations are kept transposed (features x voxels), so each layer is
+// D = W H^T with the weights as the MFMA A operand and the activations as B.
+// gfx950's v_mfma_f32_16x16x32_bf16: lane l of A holds row l%16 and eight
+// values of k, lane l of B column l%16 and the same eight k, lane l of D
+// column l%16 and rows 4(l/16)..+3.  A contraction may number its k in any
+// order that A and B share; here k = 8 kq + j (kq = l/16, j = 0..7) of K-block
+// b is feature 32 b + 16 (j/4) + 4 kq + j%4.  Then the D fragments of output
+// blocks 2b and 2b + 1, side by side, are exactly the B fragment of K-block b
+// of the next layer, so activations never leave registers, and a lane's A
+// fragment is two 8-byte runs of one weight row.  One wave handles 16 voxels.
+// Weights are staged in LDS as BF16 (round to nearest even) in rows padded to
+// 72 entries, so the 8-byte reads of half a wave fall on distinct banks.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int WROW = 72;  // padded LDS row of a BF16 weight matrix
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
     uint32_t u = __float_as_uint(f);
@@ -91,8 +99,8 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
     return (unsigned short)(u >> 16);
 }
 
-__device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-    bf16x4 r;
+__device__ __forceinline__ s16x4 pack4(float a, float b, float c, float d) {
+    s16x4 r;
     r[0] = (short)f2bf(a);
     r[1] = (short)f2bf(b);
     r[2] = (short)f2bf(c);
@@ -100,9 +108,21 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
     return r;
 }
 
+__device__ __forceinline__ bf16x8 cat8(s16x4 lo, s16x4 hi) {
+    return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+// A fragment of rows 16 mb + col, K-block b, for the lane of k-quarter kq
+__device__ __forceinline__ bf16x8 wfrag(const unsigned short *W, int row, int b, int kq) {
+    const unsigned short *p = W + WROW * row + 32 * b + 4 * kq;
+    const uint2 lo = *reinterpret_cast<const uint2 *>(p);
+    const uint2 hi = *reinterpret_cast<const uint2 *>(p + 16);
+    return __builtin_bit_cast(bf16x8, make_uint4(lo.x, lo.y, hi.x, hi.y));
+}
+
 __global__ __launch_bounds__(256) void k_query_bf16(const RobotInfo *robots, const float *genomes, const float *B,
                                                     uint8_t *cls, float *w) {
-    __shared__ unsigned short W1s[64 * 64], W2s[64 * 64], W3s[16 * 64];
+    __shared__ __align__(16) unsigned short W1s[64 * WROW], W2s[64 * WROW], W3s[16 * WROW];
     __shared__ float bias[64 + 64 + 6];
     __shared__ float Bs[3 * SR_PE_M];
     const int r = blockIdx.x;
@@ -110,10 +130,12 @@ __global__ __launch_bounds__(256) void k_query_bf16(const RobotInfo *robots, con
     const int n = ri.n, nv = n * n * n;
     const float *g = genomes + (size_t)r * SR_GENOME_LEN;
     for (int q = threadIdx.x; q < 64 * 64; q += 256) {
-        W1s[q] = f2bf(g[OFF_W1 + q]);
-        W2s[q] = f2bf(g[OFF_W2 + q]);
+        const int o = WROW * (q >> 6) + (q & 63);
+        W1s[o] = f2bf(g[OFF_W1 + q]);
+        W2s[o] = f2bf(g[OFF_W2 + q]);
     }
-    for (int q = threadIdx.x; q < 16 * 64; q += 256) W3s[q] = q < 6 * 64 ? f2bf(g[OFF_W3 + q]) : 0;
+    for (int q = threadIdx.x; q < 16 * 64; q += 256)
+        W3s[WROW * (q >> 6) + (q & 63)] = q < 6 * 64 ? f2bf(g[OFF_W3 + q]) : 0;
     for (int q = threadIdx.x; q < 64; q += 256) {
         bias[q] = g[OFF_B1 + q];
         bias[64 + q] = g[OFF_B2 + q];
@@ -129,42 +151,35 @@ __global__ __launch_bounds__(256) void k_query_bf16(const RobotInfo *robots, con
         const int vid = v0 + col;
         const int vc = vid < nv ? vid : nv - 1;
         const float vx = ((vc % n) + 0.5f) * inv, vy = (((vc / n) % n) + 0.5f) * inv, vz = ((vc / (n * n)) + 0.5f) * inv;
-        // B fragments of gamma(v): feature 16 kb + 4 kq + i of voxel `col`
-        bf16x4 X[4];
+        // gamma(v) in 16-feature blocks X[m] (features 16 m + 4 kq + i of voxel `col`):
+        // blocks 0, 1 are cos(2 pi b_q . v) and blocks 2, 3 sin of the same q
+        s16x4 X[4];
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            float f[4];
+        for (int m = 0; m < 2; ++m) {
+            float cs[4], sn[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int j = 16 * kb + 4 * kq + i;
-                const int q = j & 31;
+                const int q = 16 * m + 4 * kq + i;
                 const float t = 2.0f * fmaf(Bs[3 * q + 2], vz, fmaf(Bs[3 * q + 1], vy, Bs[3 * q] * vx));
-                float sn, cs;
-                sincospif(t, &sn, &cs);
-                f[i] = j < 32 ? cs : sn;
+                sincospif(t, &sn[i], &cs[i]);
             }
-            X[kb] = pack4(f[0], f[1], f[2], f[3]);
+            X[m] = pack4(cs[0], cs[1], cs[2], cs[3]);
+            X[m + 2] = pack4(sn[0], sn[1], sn[2], sn[3]);
         }
         // two tanh layers
-        bf16x4 H[4];
+        s16x4 H[4];
 #pragma unroll
         for (int layer = 0; layer < 2; ++layer) {
             const unsigned short *W = layer == 0 ? W1s : W2s;
             const float *bb = bias + 64 * layer;
-            bf16x4 Hn[4];
+            const s16x4 *in = layer == 0 ? X : H;
+            const bf16x8 b0 = cat8(in[0], in[1]), b1 = cat8(in[2], in[3]);
+            s16x4 Hn[4];
 #pragma unroll
             for (int mb = 0; mb < 4; ++mb) {
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int kb = 0; kb < 4; ++kb) {
-                    const unsigned short *wr = W + 64 * (16 * mb + col) + 16 * kb + 4 * kq;
-                    bf16x4 a;
-                    a[0] = (short)wr[0];
-                    a[1] = (short)wr[1];
-                    a[2] = (short)wr[2];
-                    a[3] = (short)wr[3];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, layer == 0 ? X[kb] : H[kb], acc, 0, 0, 0);
-                }
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfrag(W, 16 * mb + col, 0, kq), b0, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfrag(W, 16 * mb + col, 1, kq), b1, acc, 0, 0, 0);
                 const int f0 = 16 * mb + 4 * kq;
                 Hn[mb] = pack4(tanhf(acc[0] + bb[f0]), tanhf(acc[1] + bb[f0 + 1]), tanhf(acc[2] + bb[f0 + 2]),
                                tanhf(acc[3] + bb[f0 + 3]));
@@ -174,16 +189,8 @@ __global__ __launch_bounds__(256) void k_query_bf16(const RobotInfo *robots, con
         }
         // output layer: rows 0..5 of a 16-row block
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            const unsigned short *wr = W3s + 64 * col + 16 * kb + 4 * kq;
-            bf16x4 a;
-            a[0] = (short)wr[0];
-            a[1] = (short)wr[1];
-            a[2] = (short)wr[2];
-            a[3] = (short)wr[3];
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, H[kb], acc, 0, 0, 0);
-        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfrag(W3s, col, 0, kq), cat8(H[0], H[1]), acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wfrag(W3s, col, 1, kq), cat8(H[2], H[3]), acc, 0, 0, 0);
         // lane col (kq = 0) holds o0..o3, lane col + 16 (kq = 1) holds o4, o5
         const float o4 = __shfl(acc[0], col + 16, 64);
         const float o5 = __shfl(acc[1], col + 16, 64);
