@@ -1148,12 +1148,6 @@ constexpr size_t lds_ok() {
         NN, BS, VAR + 4 * F + 8 * (1 - W), k_persist<NN + 1, BS, VAR, F, false, false, W>,              \
             k_persist<NN + 1, BS, VAR, F, true, false, W>, lds_ok<lds_bytes<NN + 1, BS, VAR>()>()                 \
     }
-#define SR_PLS(NN, BS, F, LF, LB)                                                                          \
-    {                                                                                                        \
-        NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072,                                             \
-            k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, true>,                  \
-            k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, true>, lds_ok<lds_bytes<NN + 1, BS, 1>()>() \
-    }
 #define SR_PLF(NN, BS, F, LF, LB, BSW)                                                                     \
     {                                                                                                        \
         NN, BS, 1 + 4 * F + 256 * LF + 4096 * (LB + 1) + 131072 * BSW + 262144,                              \
@@ -1227,12 +1221,12 @@ const PersistEntry kPersist[] = {
     // defaults
     SR_PE(1, 64, 1, 0, 1),      SR_PE(2, 64, 1, 0, 1),      SR_PE(3, 64, 1, 0, 1),
     SR_PLF(4, 128, 0, 3, 3, 1), SR_PLF(5, 256, 0, 3, 3, 1), SR_PLF(6, 384, 0, 3, 3, 1), SR_PLF(7, 512, 0, 3, 3, 1),
-    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLSC(10, 512, 0, 12, 3),
-    SR_PLT(11, 896, 0, 2, 2, 0, 1), SR_PLT(12, 768, 0, 3, 2, 1, 1),
+    SR_PLF(8, 768, 0, 3, 3, 1), SR_PLF(9, 1024, 0, 3, 3, 1), SR_PLT(10, 768, 0, 2, 2, 0, 1),
+    SR_PLT(11, 1024, 0, 2, 2, 0, 1), SR_PLT(12, 768, 0, 3, 2, 1, 1),
     // the next best measured
-    SR_PLT(11, 896, 0, 3, 3, 0, 1), SR_PLT(12, 768, 0, 2, 2, 1, 1),
-    SR_PLS(10, 512, 0, 12, 3), SR_PLF(10, 448, 0, 3, 3, 1),
-    SR_PRUC(11, 896, 1, 1, 1, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4), SR_PRUC(12, 768, 2, 1, 1, 3),
+    SR_PLT(10, 768, 0, 3, 3, 0, 1), SR_PLSC(10, 512, 0, 12, 3),
+    SR_PLT(11, 896, 0, 2, 2, 0, 1), SR_PRUC(11, 896, 1, 1, 1, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4),
+    SR_PLT(12, 768, 0, 2, 2, 1, 1), SR_PRUC(12, 768, 2, 1, 1, 3),
     // plain one-chunk exchange (cross-check of the pipelined forms) and the recompute variant
     SR_PE(4, 128, 1, 0, 1),     SR_PE(5, 256, 1, 0, 1),     SR_PE(6, 384, 1, 0, 1),     SR_PE(7, 512, 1, 0, 1),
     SR_PE(8, 768, 1, 0, 1),     SR_PE(9, 1024, 1, 0, 1),    SR_PE(10, 512, 1, 0, 1),    SR_PE(10, 704, 0, 0, 1),
