@@ -169,6 +169,43 @@ def test_divergence_is_flagged_and_isolated(orc):
     assert fit[2] == -math.inf and np.all(np.isfinite(np.delete(fit, 2)))
 
 
+def test_divergence_freezes_at_launch_boundaries(orc):
+    """The GPU checks for divergence at the end of each persistent launch, the
+    oracle at the end of each call.  With 50 steps per launch and the oracle
+    stepped in calls of 50, both flag the stiff robot at the same boundary and
+    step it no further; the other robots follow the oracle."""
+    cls, w = voxel_population(C1, 29)
+    P = gpu_population(C1, cls, w)
+    P.set_step_config(SR_STEP_PERSISTENT, 0, 50)
+    M, S, mo, so = P.counts()
+    k = P.springs()["k"]
+    k[so[2]:so[3]] = 1e12
+    P.set_spring_params(k=k)
+    robots = oracle_robots(orc, C1, cls, w)
+    robots[2].set_springs(k=np.full(len(robots[2].springs()["k"]), 1e12))
+    P.step(100)
+    x100 = P.state()[0].cpu().numpy().copy()
+    for R in robots:
+        for _ in range(2):
+            R.step(50)
+    o100 = robots[2].state()[0].copy()
+    P.step(100)
+    for R in robots:
+        for _ in range(2):
+            R.step(50)
+    st = P.status().cpu().numpy()
+    assert st.tolist() == [0, 0, 1, 0, 0, 0, 0, 0]
+    assert robots[2].fitness() == -math.inf and robots[2].state()[3]
+    x200 = P.state()[0].cpu().numpy()
+    r2 = slice(mo[2], mo[3])
+    assert np.array_equal(x200[r2], x100[r2], equal_nan=True)      # frozen on the GPU
+    assert np.array_equal(robots[2].state()[0], o100, equal_nan=True)  # and in the oracle
+    xs, _, _ = gpu_states(P)
+    for r, R in enumerate(robots):
+        if r != 2:
+            assert rel_err(xs[r], R.state()[0]) <= 1e-3, r
+
+
 def test_uneven_sizes_parity(orc):
     sides = list(range(1, 13))
     cls, w = voxel_population(sides, 31)
