@@ -225,7 +225,8 @@ def uneven_generations(api, inputs, torch, R, gens, steps, tune_cache):
            "spring_updates_per_s": springs * steps / wall, "sim_spring_updates_per_s": springs * steps / sim_s,
            "seconds": wall, "sim_seconds": sim_s, "generations": gens,
            "kernels": {str(q): P.kernel_config(q) for q in sorted(set(sides))},
-           "tuned": {str(k): list(v) for k, v in tuned.items()}}
+           "tuned": {str(k): list(v) for k, v in tuned.items()},
+           "schedule": dict(zip(("sides", "lanes"), P.schedule()))}
     P.close()
     return out
 

@@ -201,6 +201,20 @@ int pop_set_graphs(sr_pop *pop, int32_t enable);
  * kind give bit-identical results.  SR_EUNSUPPORTED for a combination the
  * library lacks or that does not match the population's physics. */
 int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t variant);
+/* Launch schedule of the persistent step kernels (batching of uneven
+ * populations, the paper's one-robot-per-block launch generalised to several
+ * grid sides, Sec. II-C): the population's robots of one side form a group,
+ * launched as one kernel per block of steps.  sides (host, n entries) lists
+ * every side present, once, in launch order; lanes (host, n entries) puts
+ * each on a stream: 0 is the population's stream, k in 1..n-1 a private one.
+ * Groups on one lane run one after another; lanes run side by side (forked
+ * from and joined back into the population's stream, also inside captured
+ * step graphs).  Results do not depend on the schedule.  Default: largest
+ * side first, every group on its own lane.  SR_EINVAL unless n is the number
+ * of distinct sides and the lists are valid.  Clears the captured graphs. */
+int pop_set_schedule(sr_pop *pop, int32_t n, const int32_t *sides, const int32_t *lanes);
+/* The schedule in use (host outputs, one entry per distinct side). */
+int pop_get_schedule(sr_pop *pop, int32_t *sides, int32_t *lanes);
 /* The persistent kernel configuration in use for side n (host outputs). */
 int pop_get_persist_variant(sr_pop *pop, int32_t n, int32_t *block, int32_t *variant);
 

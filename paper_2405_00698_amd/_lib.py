@@ -65,6 +65,8 @@ _SIGS = {
     "sr_microbench": ([C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "sr_persist_configs": ([C.c_int32, P, P, C.c_int32], C.c_int),
     "pop_get_persist_variant": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "pop_set_schedule": ([P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+    "pop_get_schedule": ([P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
     "pop_record": ([P, C.c_int32, C.c_int32], C.c_int),
     "pop_backward": ([P, P, P, P, P, P, P, P], C.c_int),
     "ga_generation": ([P, P, P, C.c_int32, C.c_int32, C.POINTER(GAParams), C.c_uint64, C.c_uint64, P, P],

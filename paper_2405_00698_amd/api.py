@@ -86,6 +86,20 @@ class Population:
         check(_lib.load().pop_get_persist_variant(self.h, int(n), C.byref(b), C.byref(v)))
         return b.value, v.value
 
+    def set_schedule(self, sides, lanes):
+        """pop_set_schedule: launch order of the size groups and the stream
+        (lane) of each; lane 0 is the population's stream."""
+        n = len(sides)
+        sa, la = (C.c_int32 * n)(*[int(q) for q in sides]), (C.c_int32 * n)(*[int(q) for q in lanes])
+        check(_lib.load().pop_set_schedule(self.h, n, sa, la))
+
+    def schedule(self):
+        """(sides in launch order, their lanes)."""
+        n = len(set(self.sides))
+        sa, la = (C.c_int32 * n)(), (C.c_int32 * n)()
+        check(_lib.load().pop_get_schedule(self.h, sa, la))
+        return list(sa), list(la)
+
     def kernel_config(self, n):
         b, v = self.persist_variant(n)
         return "k_persist<%d, %d, %d>" % (n + 1, b, v)

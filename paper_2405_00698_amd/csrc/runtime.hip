@@ -97,6 +97,9 @@ struct sr_pop {
     int sc_cap = 0;
     int32_t *d_lists = nullptr;
     std::vector<SideGroup> groups;
+    // persistent-step schedule: size groups in launch order, each on a lane
+    // (0: the population's stream, k > 0: side[k - 1])
+    std::vector<int> order, lane;
     int64_t *d_mass_off = nullptr, *d_spring_off = nullptr;
     std::vector<int64_t> h_mass_off, h_spring_off;
     bool counts_valid = false;
@@ -448,6 +451,15 @@ int pop_create(const sr_sim_params *params, int32_t n_robots, const int32_t *gri
         lists.insert(lists.end(), kv.second.begin(), kv.second.end());
         pop->groups.push_back(g);
     }
+    // default schedule: largest side first, each group on a lane of its own
+    {
+        const int G = (int)pop->groups.size();
+        pop->lane.assign(G, 0);
+        for (int q = 0; q < G; ++q) {
+            pop->order.push_back(G - 1 - q);
+            pop->lane[G - 1 - q] = q;
+        }
+    }
     int rc = SR_OK;
     // private streams (default priority) for capturing step graphs: one per
     // extra size group, so the groups become parallel branches of one graph
@@ -536,6 +548,38 @@ int pop_set_step_config(sr_pop *pop, int32_t mode, int32_t block, int32_t steps_
     return SR_OK;
 }
 
+int pop_set_schedule(sr_pop *pop, int32_t n, const int32_t *sides, const int32_t *lanes) {
+    CHECK_POP(pop);
+    const int G = (int)pop->groups.size();
+    if (n != G) return set_err(SR_EINVAL, "schedule of %d sides for a population of %d", n, G);
+    if (!sides || !lanes) return set_err(SR_EINVAL, "null schedule");
+    std::vector<int> order, lane(G, -1);
+    for (int q = 0; q < n; ++q) {
+        int g = -1;
+        for (int h = 0; h < G; ++h)
+            if (pop->groups[h].n == sides[q]) g = h;
+        if (g < 0) return set_err(SR_EINVAL, "no robot of side %d", sides[q]);
+        if (lane[g] >= 0) return set_err(SR_EINVAL, "side %d listed twice", sides[q]);
+        if (lanes[q] < 0 || lanes[q] >= G) return set_err(SR_EINVAL, "lane %d outside 0..%d", lanes[q], G - 1);
+        lane[g] = lanes[q];
+        order.push_back(g);
+    }
+    pop->order = order;
+    pop->lane = lane;
+    clear_graphs(pop);
+    return SR_OK;
+}
+
+int pop_get_schedule(sr_pop *pop, int32_t *sides, int32_t *lanes) {
+    CHECK_POP(pop);
+    if (!sides || !lanes) return set_err(SR_EINVAL, "null output");
+    for (size_t q = 0; q < pop->order.size(); ++q) {
+        sides[q] = pop->groups[pop->order[q]].n;
+        lanes[q] = pop->lane[pop->order[q]];
+    }
+    return SR_OK;
+}
+
 int pop_set_persist_variant(sr_pop *pop, int32_t n, int32_t block, int32_t variant) {
     CHECK_POP(pop);
     for (auto &g : pop->groups)
@@ -587,26 +631,32 @@ int enqueue_steps(sr_pop *pop, int n_steps, float2 *sc, hipStream_t st) {
         HIPC(pop, launch_check_div(pop->d_robots, pop->R, pop->xbuf[pop->cur], pop->vbuf[pop->cur], pop->diverged,
                                    pop->c.lim, st));
     } else {
+        // the size groups in the schedule's order, each on its lane's stream;
+        // the lanes fork from and join back into st
         const int G = (int)pop->groups.size();
+        bool used[SR_MAX_SIDE] = {};  // at most one group per side
+        for (int g = 0; g < G; ++g) used[pop->lane[g]] = true;
         if (G > 1) {
             HIPC(pop, hipEventRecord(pop->ev[0], st));
-            for (int g = 1; g < G; ++g) HIPC(pop, hipStreamWaitEvent(pop->side[g - 1], pop->ev[0], 0));
+            for (int l = 1; l < G; ++l)
+                if (used[l]) HIPC(pop, hipStreamWaitEvent(pop->side[l - 1], pop->ev[0], 0));
         }
-        // largest robots first: group G-1 has the largest side
         for (int t0 = 0; t0 < n_steps; t0 += spl) {
             const int cnt = (n_steps - t0) < spl ? (n_steps - t0) : spl;
             for (int q = 0; q < G; ++q) {
-                const SideGroup &gr = pop->groups[G - 1 - q];
-                hipStream_t sq = q == 0 ? st : pop->side[q - 1];
+                const int g = pop->order[q];
+                const SideGroup &gr = pop->groups[g];
+                hipStream_t sq = pop->lane[g] == 0 ? st : pop->side[pop->lane[g] - 1];
                 HIPC(pop, launch_persistent(gr.cfg, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count,
                                             gr.count, pop->pl, pop->xbuf[pop->cur], pop->vbuf[pop->cur],
                                             sc + t0, cnt, pop->diverged, pop->c, sq));
             }
         }
-        for (int q = 1; q < G; ++q) {
-            HIPC(pop, hipEventRecord(pop->ev[q], pop->side[q - 1]));
-            HIPC(pop, hipStreamWaitEvent(st, pop->ev[q], 0));
-        }
+        for (int l = 1; l < G; ++l)
+            if (used[l]) {
+                HIPC(pop, hipEventRecord(pop->ev[l], pop->side[l - 1]));
+                HIPC(pop, hipStreamWaitEvent(st, pop->ev[l], 0));
+            }
     }
     HIPC(pop, launch_advance(pop->d_step, n_steps, st));
     return SR_OK;

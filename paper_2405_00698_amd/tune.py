@@ -1,8 +1,10 @@
 """Tuner for the persistent step kernel: for every grid side present in a
 population, times each compiled (workgroup size, exchange variant)
-configuration on the live population and keeps the fastest; then times the
-number of steps per launch (the whole call, or the call split into shorter
-launches) on the whole population.  Results are cached in a JSON file keyed by
+configuration on the live population and keeps the fastest; then, with several
+grid sides, times a few launch schedules of the size groups (which stream each
+side's launch goes to, in which order); then the number of steps per launch
+(the whole call, or the call split into shorter launches) on the whole
+population.  Results are cached in a JSON file keyed by
 (device name, side, population bucket, spring model, the library's
 configuration list for that side)."""
 import hashlib
@@ -103,6 +105,30 @@ def tune(pop, steps=200, cache_path=None, verbose=False):
         pop.set_persist_variant(n, best[0], best[1])
         result[n] = best
         cache[key] = list(best)
+    # launch schedule of the size groups (several sides only): each side's
+    # launch on a stream of its own, largest first (the default), or the
+    # sides dealt largest first round-robin over 2..4 streams, or over three
+    # streams back and forth
+    if len(counts) > 1:
+        desc = sorted(counts, reverse=True)
+        ckey = "%s|sched|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
+                                   ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())))
+        cands = [list(range(len(desc)))] + [[i % k for i in range(len(desc))] for k in (2, 3, 4)]
+        cands.append([(i // 3 % 2) * (2 - i % 3) + (1 - i // 3 % 2) * (i % 3) for i in range(len(desc))])
+        if ckey in cache:
+            lanes = list(cache[ckey])
+        else:
+            times = []
+            for lanes in cands:
+                pop.set_schedule(desc, lanes)
+                t = _time(pop, steps)
+                if verbose:
+                    print("schedule %s: %.4f s" % (lanes, t), flush=True)
+                times.append((lanes, t))
+            best = min(times, key=lambda q: q[1])
+            lanes = cands[0] if times[0][1] <= 1.03 * best[1] else best[0]
+            cache[ckey] = lanes
+        pop.set_schedule(desc, lanes)
     # steps per launch, on the whole population with the configurations above
     skey = "%s|spl|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
                              ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())))

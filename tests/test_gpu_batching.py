@@ -35,6 +35,35 @@ def test_graphs_match_direct_launches_bitwise(plain):
         assert np.array_equal(a, b)
 
 
+def test_launch_schedules_give_the_same_bits():
+    """Every size group computes only its own robots, so the order of the
+    groups' launches and the streams they go to change no result; the
+    schedule travels into captured graphs and is validated."""
+    from paper_2405_00698_amd import SoftRobotError
+    sides = [int(n) for n in inputs.grid_sides(40, 4, 12)]
+    cls, w = voxel_population(sides, 63)
+    P = gpu_population(sides, cls, w)
+    desc = sorted(set(sides), reverse=True)
+    assert P.schedule() == (desc, list(range(len(desc))))
+    P.set_step_config(steps_per_launch=40)
+    P.step(120)
+    ref = P.state()[0].cpu().numpy()
+    scheds = [(desc, [i % 2 for i in range(len(desc))]), (desc[::-1], [0] * len(desc)),
+              (desc, [(3 * i) % len(desc) for i in range(len(desc))])]
+    for order, lanes in scheds:
+        P.set_schedule(order, lanes)
+        assert P.schedule() == (list(order), list(lanes))
+        for graphs in (True, False):
+            P.set_graphs(graphs)
+            P.reset()
+            P.step(120)
+            assert np.array_equal(P.state()[0].cpu().numpy(), ref), (order, lanes, graphs)
+    for order, lanes in ((desc[1:], list(range(len(desc) - 1))), (desc, [len(desc)] * len(desc)),
+                         ([desc[0]] * len(desc), list(range(len(desc)))), ([13] + desc[1:], list(range(len(desc))))):
+        with pytest.raises(SoftRobotError):
+            P.set_schedule(order, lanes)
+
+
 def test_tuner_picks_a_compiled_config_and_keeps_results(tmp_path):
     from paper_2405_00698_amd import tune, api
     sides = [6] * 16 + [10] * 16
@@ -48,8 +77,10 @@ def test_tuner_picks_a_compiled_config_and_keeps_results(tmp_path):
         assert P.persist_variant(n) == (b, v)
     P.step(150)
     assert np.array_equal(P.state()[0].cpu().numpy(), ref)
+    sched = P.schedule()
     res2 = tune.tune(P, steps=50, cache_path=str(tmp_path / "tune.json"))
     assert {n: r[:2] for n, r in res.items()} == {n: r[:2] for n, r in res2.items()}
+    assert P.schedule() == sched
 
 
 def test_uneven_codesign_loop_is_reproducible():
