@@ -196,7 +196,9 @@ int pop_set_graphs(sr_pop *pop, int32_t enable);
  *   +1048576 pads each coefficient row only by its own stencil offset (less
  *     LDS, for the one-chunk exchange at the largest sides);
  *   +2097152 + 4194304 * (U - 1) leaves the direction loops rolled (unrolled
- *     by U), with every parameter rebuilt from voxels.
+ *     by U), with every parameter rebuilt from voxels;
+ *   +16777216 * (P - 1) steps P robots in one workgroup (block / P threads
+ *     each), for small grids.
  * sr_persist_configs lists the compiled combinations.  All variants of one
  * kind give bit-identical results.  SR_EUNSUPPORTED for a combination the
  * library lacks or that does not match the population's physics. */

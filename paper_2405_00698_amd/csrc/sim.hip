@@ -424,6 +424,8 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 //   CLS    the balanced slot plan: runs of 64 slots, top- and bottom-plane runs
 //          skip the directions that leave the lattice
 //   TCR    tight coefficient rows (one-chunk exchange, above)
+//   PK     robots per workgroup: PK robots of BS / PK threads each, every one
+//          with its own LDS, stepping together (small grids)
 //
 // LAG (exchange variants, 16-byte reads): the neighbour reads of a slot are
 // issued back to back with at most LAG + 1 outstanding; the read LAG places
@@ -437,8 +439,11 @@ __device__ __forceinline__ void vox_store(float4 &d, float4 v) { d = v; }
 // coefficient as soon as it is computed).
 template <int N, int BS, int VAR, bool FENCE, bool PHASE, bool REC = false, bool WIDE = true, bool DASH = false,
           int VOX = 0, bool SBX = false, int LAG = 0, int LAGB = -1, bool BSWP = false, bool FSWP = false,
-          int ROLL = 0, bool CLS = false, bool TCR = false>
+          int ROLL = 0, bool CLS = false, bool TCR = false, int PK = 1>
 __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
+    constexpr int BR = BS / PK;  // threads per robot
+    static_assert(BS % PK == 0 && BR % 64 == 0, "whole waves per robot");
+    static_assert(PK == 1 || (!CLS && !REC && ROLL == 0), "packed robots use the plain slot mapping");
     static_assert(!TCR || (VAR == 1 && ROLL == 0), "tight coefficient rows hold one chunk of unrolled directions");
     static_assert(!CLS || VAR == 1 || ROLL > 0,
                   "the balanced slot plan skips directions in the one-chunk or the rolled exchange");
@@ -453,28 +458,36 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                   "pipelined reads need the one-chunk exchange (constant direction indices)");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
-    constexpr int NPT = (SL + BS - 1) / BS;
+    constexpr int NPT = (SL + BR - 1) / BR;
     constexpr int NCH = VAR == 0 ? 1 : VAR;
     constexpr int NDC = VAR == 0 ? 0 : (NDIR + VAR - 1) / VAR;
     constexpr int NQ = VAR == 0 ? NDIR : 1;  // backward parameter copies (recompute variant)
     constexpr int NB = PHASE ? NDIR : 1;
     // three distinct LDS objects, so the compiler knows coefficient stores
     // never alias position loads and can keep many loads in flight
-    __shared__ float4 xb0[XL];
-    __shared__ float4 xb1[SBX ? 1 : XL];
     constexpr int CLEN = NDC > 0 ? coef_len<N, NDC, TCR>() : 1;
-    __shared__ float coef[CLEN];
-    __shared__ float4 vb[DASH ? XL : 1];
     typedef typename VoxT<PHASE || DASH>::T VT;
-    __shared__ VT vv[VOX ? CL : 1];
-    __shared__ int bad;
+    __shared__ float4 xb0s[PK * XL];
+    __shared__ float4 xb1s[SBX ? 1 : PK * XL];
+    __shared__ float coefs[PK * CLEN];
+    __shared__ float4 vbs[DASH ? PK * XL : 1];
+    __shared__ VT vvs[VOX ? PK * CL : 1];
+    __shared__ int bads[PK];
     const int tid = threadIdx.x;
+    // this thread's robot j of the workgroup and its index lt among that robot's threads
+    const int j = PK == 1 ? 0 : tid / BR, lt = PK == 1 ? tid : tid % BR;
+    float4 *const xb0 = xb0s + j * XL;
+    float4 *const xb1 = SBX ? xb1s : xb1s + j * XL;
+    float *const coef = coefs + j * CLEN;
+    float4 *const vb = DASH ? vbs + j * XL : vbs;
+    VT *const vv = VOX ? vvs + j * CL : vvs;
+    int &bad = bads[j];
     const SimConst c = A.c;
-    // the lattice slot of each of this thread's NPT places: slot tid + k BS,
+    // the lattice slot of each of this thread's NPT places: slot lt + k BR,
     // or (CLS) lane tid mod 64 of the run the balanced plan gives the wave;
     // top / bot: the wave's run lies in the top / bottom plane
     int sk[NPT];
-    bool lk[NPT], topk[NPT], botk[NPT];
+    bool lk0[NPT], topk[NPT], botk[NPT];
     {
         const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
 #pragma unroll
@@ -484,30 +497,37 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 constexpr SlotPlan<N, BS> plan = make_slot_plan<N, BS>();
                 const int u = plan.unit[k][w];
                 sk[k] = 64 * u + (tid & 63);
-                lk[k] = u >= 0 && sk[k] < SL;
+                lk0[k] = u >= 0 && sk[k] < SL;
                 // wave-uniform (scalar) so that branches and loop bounds on them stay scalar
                 topk[k] = __builtin_amdgcn_readfirstlane(u >= 0 && run_class<N>(u) == RUN_TOP ? 1 : 0) != 0;
                 botk[k] = __builtin_amdgcn_readfirstlane(u >= 0 && run_class<N>(u) == RUN_BOTTOM ? 1 : 0) != 0;
             } else {
-                sk[k] = tid + k * BS;
-                lk[k] = sk[k] < SL;
+                sk[k] = lt + k * BR;
+                lk0[k] = sk[k] < SL;
                 topk[k] = false;
                 botk[k] = false;
             }
         }
     }
 
-    for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
-        const int r = A.list[q];
-        if (A.diverged[r]) continue;
-        const int base = A.robots[r].slot_base;
+    for (int q0 = blockIdx.x * PK; q0 < A.count; q0 += gridDim.x * PK) {
+        // a packed workgroup steps all its robots together: one without a
+        // robot (or with a diverged one) has no live slot but keeps the barriers
+        const int q = q0 + j;
+        const int r = q < A.count ? A.list[q] : 0;
+        const bool act = q < A.count && !A.diverged[r];
+        if (PK == 1 && !act) continue;
+        bool lk[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) lk[k] = lk0[k] && act;
+        const int base = act ? A.robots[r].slot_base : 0;
         const int pbase = NDIR * base;
         const float lim = c.lim * (N - 1);
 
         if (VAR != 0)
-            for (int i = tid; i < CLEN; i += BS) coef[i] = 0.f;
+            for (int i = lt; i < CLEN; i += BR) coef[i] = 0.f;
         const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f);
-        for (int i = tid; i < PAD; i += BS) {
+        for (int i = lt; i < PAD; i += BR) {
             xb0[i] = ghost;
             xb0[PAD + SL + i] = ghost;
             if constexpr (!SBX) {
@@ -520,7 +540,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 vb[PAD + SL + i] = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
-        if (tid == 0) bad = 0;
+        if (lt == 0) bad = 0;
 
         float3 xr[NPT], vr[NPT];
         bool pres[NPT];
@@ -1007,7 +1027,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
         }
         if (mybad) bad = 1;
         __syncthreads();
-        if (tid == 0 && bad) A.diverged[r] = 1;
+        if (lt == 0 && bad && act) A.diverged[r] = 1;
         __syncthreads();
     }
 }
@@ -1121,6 +1141,7 @@ struct PersistEntry {
     int n, block, variant;
     PersistFn fn, fn_phase;
     size_t lds;
+    int pack = 1;  // robots per workgroup
 };
 
 // Variant codes (the sum documented at pop_set_persist_variant): exchange
@@ -1134,7 +1155,8 @@ struct PersistEntry {
 // loops with every parameter from voxels, + 4194304 * (U - 1) unrolled by U;
 // + 524288 the balanced slot plan (top- and bottom-plane runs skip the
 // directions that leave the lattice, runs dealt evenly over the SIMDs);
-// + 1048576 tight coefficient rows.
+// + 1048576 tight coefficient rows; + 16777216 * (PK - 1) PK robots per
+// workgroup.
 // Every entry's LDS arrays must fit one CU's 160 KiB (checked at compile time
 // here, and for the code objects as built by a CPU test, since the compiler may
 // add LDS of its own).
@@ -1163,6 +1185,14 @@ constexpr size_t lds_ok() {
             k_persist<NN + 1, BS, 1, F, false, false, true, false, 0, false, LF, LB, true, false, 0, true>,  \
             k_persist<NN + 1, BS, 1, F, true, false, true, false, 0, false, LF, LB, true, false, 0, true>,   \
             lds_ok<lds_bytes<NN + 1, BS, 1>()>()                                                                       \
+    }
+// several small robots per workgroup (the default pipelined form)
+#define SR_PLFP(NN, BR, PK)                                                                                  \
+    {                                                                                                        \
+        NN, BR * PK, 1 + 256 * 3 + 4096 * 4 + 131072 + 262144 + 16777216 * (PK - 1),                         \
+            k_persist<NN + 1, BR * PK, 1, false, false, false, true, false, 0, false, 3, 3, true, true, 0, false, false, PK>, \
+            k_persist<NN + 1, BR * PK, 1, false, true, false, true, false, 0, false, 3, 3, true, true, 0, false, false, PK>,  \
+            lds_ok<PK * lds_bytes<NN + 1, BR * PK, 1>()>(), PK                                                \
     }
 // + 1048576: tight coefficient rows (with the balanced slot plan, software-
 // pipelined backward springs, optionally pipelined forward ones and one
@@ -1227,6 +1257,8 @@ const PersistEntry kPersist[] = {
     SR_PLT(10, 768, 0, 3, 3, 0, 1), SR_PLSC(10, 512, 0, 12, 3),
     SR_PLT(11, 896, 0, 2, 2, 0, 1), SR_PRUC(11, 896, 1, 1, 1, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4),
     SR_PLT(12, 768, 0, 2, 2, 1, 1), SR_PRUC(12, 768, 2, 1, 1, 3),
+    // several small robots per workgroup (measured slower in the uneven population)
+    SR_PLFP(4, 128, 4), SR_PLFP(5, 256, 2), SR_PLFP(6, 384, 2),
     // plain one-chunk exchange (cross-check of the pipelined forms) and the recompute variant
     SR_PE(4, 128, 1, 0, 1),     SR_PE(5, 256, 1, 0, 1),     SR_PE(6, 384, 1, 0, 1),     SR_PE(7, 512, 1, 0, 1),
     SR_PE(8, 768, 1, 0, 1),     SR_PE(9, 1024, 1, 0, 1),    SR_PE(10, 512, 1, 0, 1),    SR_PE(10, 704, 0, 0, 1),
@@ -1324,7 +1356,7 @@ hipError_t launch_persistent(const PersistCfg &cfg, bool phase, const RobotInfo 
     A.rec_v = nullptr;
     A.rec_u = nullptr;
     PersistFn fn = phase ? e->fn_phase : e->fn;
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(e->block), 0, st, A);
+    hipLaunchKernelGGL(fn, dim3((grid + e->pack - 1) / e->pack), dim3(e->block), 0, st, A);
     return hipGetLastError();
 }
 

@@ -206,6 +206,33 @@ def test_divergence_freezes_at_launch_boundaries(orc):
             assert rel_err(xs[r], R.state()[0]) <= 1e-3, r
 
 
+@pytest.mark.parametrize("n,block,pk", [(4, 512, 4), (5, 512, 2), (6, 768, 2)])
+def test_packed_workgroups_match_one_robot_per_workgroup(n, block, pk):
+    """Several robots per workgroup, each with its own LDS: 13 robots (a
+    partial last workgroup) with one driven to diverge, in launches of 100
+    steps (so packs also hold frozen robots), against one robot per
+    workgroup, bit for bit."""
+    sides = [n] * 13
+    cls, w = voxel_population(sides, 67)
+    outs = []
+    for cfg in (None, (block, 410369 + 16777216 * (pk - 1))):
+        P = gpu_population(sides, cls, w)
+        M, S, mo, so = P.counts()
+        k = P.springs()["k"]
+        k[so[5]:so[6]] = 1e12
+        P.set_spring_params(k=k)
+        if cfg:
+            P.set_persist_variant(n, *cfg)
+            assert P.persist_variant(n) == cfg
+        P.set_step_config(SR_STEP_PERSISTENT, 0, 100)
+        P.step(300)
+        x, v, _ = P.state()
+        outs.append((x.cpu().numpy(), v.cpu().numpy(), P.status().cpu().numpy(), P.fitness().cpu().numpy()))
+    assert outs[0][2].tolist() == [0] * 5 + [1] + [0] * 7
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b, equal_nan=True)
+
+
 def test_uneven_sizes_parity(orc):
     sides = list(range(1, 13))
     cls, w = voxel_population(sides, 31)
