@@ -88,6 +88,10 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the default step-kernel configuration")
     ap.add_argument("--kernel", default=None,
                     help="BLOCK,VARIANT: run the uniform workload with this step-kernel configuration (no tuning)")
+    ap.add_argument("--only", default=None, choices=["adjoint", "uneven"],
+                    help="run just the adjoint ratio (64 x 8^3) or the uneven 1024-robot generations and print "
+                         "their figures (for profiling those workloads)")
+    ap.add_argument("--gens", type=int, default=20, help="generations of the uneven workload with --only uneven")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (HBM counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -226,7 +230,8 @@ def uneven_generations(api, inputs, torch, R, gens, steps, tune_cache):
            "seconds": wall, "sim_seconds": sim_s, "generations": gens,
            "kernels": {str(q): P.kernel_config(q) for q in sorted(set(sides))},
            "tuned": {str(k): list(v) for k, v in tuned.items()},
-           "schedule": dict(zip(("sides", "lanes"), P.schedule()))}
+           "schedule": dict(zip(("sides", "lanes"), P.schedule())),
+           "steps_per_launch": P.steps_per_launch or steps}
     P.close()
     return out
 
@@ -306,6 +311,13 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     tune_cache = "/tmp/softrobot_tune.json"
+    if args.only == "adjoint":
+        print(json.dumps({"adjoint_forward_ratio": adjoint_ratio(api, inputs, torch)}), flush=True)
+        return
+    if args.only == "uneven":
+        print(json.dumps({"c3_uneven_1024": uneven_generations(api, inputs, torch, 1024, args.gens, 10000,
+                                                               tune_cache)}), flush=True)
+        return
     R, n = args.robots, args.side
     B = inputs.gaussian_B()
     if args.workload == "uneven":
