@@ -208,9 +208,12 @@ __device__ __forceinline__ float mul_nf(float a, float b) {
 // Coefficient rows.  Uniform rows (one per direction of a chunk, CL entries
 // each): slot s stores chunk-local direction j at j CL + PAD + s, and the
 // backward read of slot s at s - off(d) stays inside the row's PAD leading
-// zeros.  Tight rows (one chunk only): row d is preceded by just off(d) zeros,
-// 13 SL + sum of off(d) entries in all, which lets the one-chunk exchange of
-// the 12^3 lattice (13^3 points) fit in LDS beside one position buffer.
+// zeros, which no chunk ever writes.  Tight rows (one chunk only): row d is
+// preceded by just off(d) zeros, 13 SL + sum of off(d) entries in all, which
+// lets the one-chunk exchange of the 12^3 lattice (13^3 points) fit in LDS
+// beside one position buffer.  (With several chunks the rows of the later
+// chunks would start elsewhere, and their leading zeros would land on the
+// coefficients the first chunk wrote.)
 template <int N>
 __host__ __device__ constexpr int tight_row(int d) {
     int r = 0;
@@ -1218,6 +1221,21 @@ constexpr size_t lds_ok() {
             k_persist<NN + 1, BS, VAR, F, true, false, true, false, VOX, SBX, LG>,                           \
             lds_ok<lds_bytes<NN + 1, BS, VAR, false, VOX, SBX>()>()                                                    \
     }
+// dashpot kernels with the balanced slot plan and tight coefficient rows
+#define SR_PDT(NN, BS, LF, LB, SBX)                                                                         \
+    {                                                                                                        \
+        NN, BS, 1 + 16 + 128 * SBX + 256 * LF + 4096 * (LB + 1) + 131072 + 262144 + 524288 + 1048576,         \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, SBX, LF, LB, true, true, 0, true, true>, \
+            k_persist<NN + 1, BS, 1, false, true, false, true, true, 0, SBX, LF, LB, true, true, 0, true, true>, \
+            lds_ok<lds_bytes<NN + 1, BS, 1, true, 0, SBX, true>()>()                                                   \
+    }
+// two-chunk dashpot exchange with one position buffer (12^3)
+#define SR_PDC(NN, BS)                                                                                       \
+    {                                                                                                        \
+        NN, BS, 2 + 16 + 128, k_persist<NN + 1, BS, 2, false, true, false, true, true, 0, true>,              \
+            k_persist<NN + 1, BS, 2, false, true, false, true, true, 0, true>,                                   \
+            lds_ok<lds_bytes<NN + 1, BS, 2, true, 0, true>()>()                                                  \
+    }
 // dashpot kernels carry the phase plane always (with a zero plane the results
 // are the same bits as without it); SR_PDF / SR_PDVF software-pipeline their
 // position and velocity reads
@@ -1265,8 +1283,9 @@ const PersistEntry kPersist[] = {
     // spring dashpots (Table II model)
     SR_PD(1, 64, 1),            SR_PD(2, 64, 1),            SR_PD(3, 64, 1),
     SR_PDF(4, 128, 3, 3),       SR_PDF(5, 256, 3, 3),       SR_PDF(6, 384, 3, 3),       SR_PDF(7, 512, 3, 3),
-    SR_PDF(8, 768, 3, 3),       SR_PDF(9, 1024, 3, 3),      SR_PDVF(10, 704, 2, 1, 3, 3),
-    SR_PD(10, 512, 1),          SR_PD(11, 512, 2),          SR_PD(12, 512, 0),          SR_PD(8, 768, 1),
+    SR_PDF(8, 768, 3, 3),       SR_PDF(9, 1024, 3, 3),      SR_PDT(10, 768, 2, 2, 1),   SR_PDT(11, 1024, 1, 1, 1),
+    SR_PDC(12, 768),            SR_PDVF(10, 704, 2, 1, 3, 3),
+    SR_PD(8, 768, 1),
 };
 
 #define SR_REC(NN, BS, VAR) \
