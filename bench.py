@@ -206,6 +206,9 @@ def uneven_generations(api, inputs, torch, R, gens, steps, tune_cache):
     P = api.Population(sides)
     P.build_from_genomes(G[0], B, SR_QUERY_BF16)
     tuned = tune.tune(P, steps=500, cache_path=tune_cache)
+    # one untimed call of the production length (captures its step graph)
+    P.step(steps)
+    P.reset()
     cfg = GAConfig()
     springs, sim_s = 0, 0.0
     torch.cuda.synchronize()

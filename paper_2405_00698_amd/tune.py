@@ -129,19 +129,23 @@ def tune(pop, steps=200, cache_path=None, verbose=False):
             lanes = cands[0] if times[0][1] <= 1.03 * best[1] else best[0]
             cache[ckey] = lanes
         pop.set_schedule(desc, lanes)
-    # steps per launch, on the whole population with the configurations above
-    skey = "%s|spl|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
-                             ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())))
+    # steps per launch, on the whole population with the configurations and
+    # schedule above: the whole call as one launch per side, or launches of
+    # 1000 or 250 steps (sides that share a stream then take turns), timed on
+    # calls of at least 2000 steps so that the launch count is representative
+    lanes = ",".join(str(q) for q in pop.schedule()[1]) if len(counts) > 1 else "-"
+    skey = "%s|spl|%s|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
+                                ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())), lanes)
     if skey in cache:
         spl = int(cache[skey])
     else:
-        cands = sorted({0, steps // 2, steps // 5} - {-1})
+        length = max(steps, 2000)
         times = []
-        for c in cands:
-            if c < 0 or (0 < c < 20):
+        for c in (0, 1000, 250):
+            if c >= length:
                 continue
             pop.set_step_config(api._lib.SR_STEP_AUTO, 0, c)
-            t = _time(pop, steps)
+            t = _time(pop, length)
             if verbose:
                 print("steps per launch %s: %.4f s" % (c or "all", t), flush=True)
             times.append((c, t))
