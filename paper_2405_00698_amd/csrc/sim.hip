@@ -1275,6 +1275,7 @@ const PersistEntry kPersist[] = {
     SR_PLT(10, 768, 0, 3, 3, 0, 1), SR_PLSC(10, 512, 0, 12, 3),
     SR_PLT(11, 896, 0, 2, 2, 0, 1), SR_PRUC(11, 896, 1, 1, 1, 3), SR_PVL(11, 256, 1, 2, 1, 1, 4),
     SR_PLT(12, 768, 0, 2, 2, 1, 1), SR_PRUC(12, 768, 2, 1, 1, 3),
+    SR_PLT(8, 768, 0, 3, 3, 0, 1),  // slot plan at 8^3: 3 % faster with one robot per CU, slower with two
     // several small robots per workgroup (measured slower in the uneven population)
     SR_PLFP(4, 128, 4), SR_PLFP(5, 256, 2), SR_PLFP(6, 384, 2),
     // plain one-chunk exchange (cross-check of the pipelined forms) and the recompute variant
