@@ -28,6 +28,7 @@ struct AArgs {
     const float4 *x0;
     const float4 *rec_x, *rec_v;  // [n_steps * slot_base + t * slots + s]
     const float4 *rec_u;          // v_n (dashpots, damped ground), same layout
+    float4 *rec_l;                // lambda_F of every step (split form), same layout
     int n_steps;
     const float2 *sc;
     float4 *lx, *lv;    // per slot
@@ -35,6 +36,21 @@ struct AArgs {
     float *gd;            // dJ/dc per stencil entry (dashpots)
     SimConst c;
 };
+
+// The parameter-gradient terms of one spring at one step (d = x_hi - x_lo,
+// u = lambda_F,hi - lambda_F,lo, r2 = |d|^2, ir = 1/r, kL = k L(t), du = d.u):
+//   dJ/dk  += -(r - L(t)) du / r,   dJ/d(k L0 a cos phi) += k du / r S,
+//   dJ/d(k L0 a sin phi) += k du / r C.
+// One helper for the fused reverse step and the split gradient pass, so both
+// take the same operations and give the same bits.
+__device__ __forceinline__ void spring_grad_sums(float r2, float ir, float kL, float du, float k, float ik, float2 sct,
+                                                 float &gk, float &gs, float &gc) {
+    const float dhu = du * ir;
+    gk = fmaf(-(r2 * ir - kL * ik), dhu, gk);
+    const float gL = k * dhu;
+    gs = fmaf(gL, sct.x, gs);
+    gc = fmaf(gL, sct.y, gc);
+}
 
 // XCH: each spring's K_s (lF_hi - lF_lo) is computed once by its lower end and
 // handed to the upper end through LDS (three rows per direction, PAD zero
@@ -58,8 +74,14 @@ struct AArgs {
 // FNC: a scheduling barrier after each direction's spring work, so the
 // compiler does not hoist every neighbour read of the slot (which spilled the
 // non-exchange form at 9^3: 1265 VGPRs without, 51 with)
-template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0, bool ONEBUF = false, bool DASH = false, bool FNC = false>
+// NOG (split form): the reverse step keeps no parameter-gradient sums; it
+// writes each step's lambda_F to rec_l instead, and k_adj_grad forms the sums
+// from the recorded positions and those lambda_F afterwards.  The 13 springs'
+// three sums per slot no longer take registers beside the adjoint recursion.
+template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0, bool ONEBUF = false, bool DASH = false, bool FNC = false,
+          bool NOG = false>
 __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
+    static_assert(!NOG || !DASH, "the split form is for the spring model without dashpots");
     static_assert(ALAG == 0 || XCH, "pipelined reads are for the exchange form");
     static_assert(!DASH || (!XCH && ONEBUF), "the dashpot adjoint is a one-buffer recompute form");
     using G = Geo<N>;
@@ -102,7 +124,8 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         float3 X0[NPT], lx[NPT], lv[NPT];
         float pk[NPT][NDIR], pa[NPT][NDIR], pb[NPT][NDIR], pik[NPT][NDIR];
         float qk[NPT][NQ], qa[NPT][NQ], qb[NPT][NQ];
-        float gk[NPT][NDIR], gs[NPT][NDIR], gc[NPT][NDIR];
+        constexpr int NG = NOG ? 1 : NDIR;
+        float gk[NPT][NG], gs[NPT][NG], gc[NPT][NG];
         float pd[NPT][DASH ? NDIR : 1], qd[NPT][DASH ? NQ : 1], gd[NPT][DASH ? NDIR : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
@@ -123,9 +146,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 pa[k][d] = live ? A.pl.kal[pi] : 0.f;
                 pb[k][d] = (live && PHASE) ? A.pl.kbe[pi] : 0.f;
                 pik[k][d] = kk != 0.f ? 1.0f / kk : 0.f;
-                gk[k][d] = live ? A.gk[pi] : 0.f;
-                gs[k][d] = live ? A.gs[pi] : 0.f;
-                gc[k][d] = live ? A.gc[pi] : 0.f;
+                if constexpr (!NOG) {
+                    gk[k][d] = live ? A.gk[pi] : 0.f;
+                    gs[k][d] = live ? A.gs[pi] : 0.f;
+                    gc[k][d] = live ? A.gc[pi] : 0.f;
+                }
                 if constexpr (DASH) {
                     pd[k][d] = live ? A.pl.kd[pi] : 0.f;
                     gd[k][d] = live ? A.gd[pi] : 0.f;
@@ -261,6 +286,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 }
                 Xr[k] = X;
                 LF[k] = lF;
+                if (NOG && pres[k]) A.rec_l[rbase + (size_t)t * SL + s] = make_float4(lF.x, lF.y, lF.z, 0.f);
                 xs[b][PAD + s] = make_float4(X.x, X.y, X.z, 0.f);
                 lf[b][PAD + s] = make_float4(lF.x, lF.y, lF.z, 0.f);
                 if constexpr (DASH) {
@@ -345,11 +371,9 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                         ku[(1 * NDIR + d) * CL + PAD + s] = ky;
                         ku[(2 * NDIR + d) * CL + PAD + s] = kz;
                     }
-                    const float dhu = du * ir;
-                    gk[k][d] = fmaf(-(r2 * ir - kL * pik[k][d]), dhu, gk[k][d]);
-                    const float gL = pk[k][d] * dhu;
-                    gs[k][d] = fmaf(gL, sct.x, gs[k][d]);
-                    gc[k][d] = fmaf(gL, sct.y, gc[k][d]);
+                    if constexpr (!NOG)
+                        spring_grad_sums(r2, ir, kL, du, pk[k][d], pik[k][d], sct, gk[k][NOG ? 0 : d], gs[k][NOG ? 0 : d],
+                                         gc[k][NOG ? 0 : d]);
                     if (FNC) __builtin_amdgcn_sched_barrier(0);
                 }
                 if (!XCH) {
@@ -437,10 +461,122 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
 #pragma unroll
             for (int d = 0; d < NDIR; ++d) {
                 const int pi = pbase + d * SL + s;
-                A.gk[pi] = gk[k][d];
-                A.gs[pi] = gs[k][d];
-                A.gc[pi] = gc[k][d];
+                if constexpr (!NOG) {
+                    A.gk[pi] = gk[k][NOG ? 0 : d];
+                    A.gs[pi] = gs[k][NOG ? 0 : d];
+                    A.gc[pi] = gc[k][NOG ? 0 : d];
+                }
                 if constexpr (DASH) A.gd[pi] = gd[k][d];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Split form, second pass: the parameter-gradient sums of the forward springs
+// of directions D0 .. D1 - 1 over one segment, from the recorded positions x_t
+// (rec_x; an absent slot sits at its build position) and the reverse step's
+// lambda_F (rec_l; zero on absent slots), step by step from the segment's end
+// to its start as in the fused form, through the same helper: the same bits.
+// One LDS buffer of positions and one of lambda_F, two barriers per step.
+template <int N, int BS, bool PHASE, int D0, int D1>
+__global__ __launch_bounds__(BS) void k_adj_grad(AArgs A) {
+    using G = Geo<N>;
+    constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL;
+    constexpr int NPT = (SL + BS - 1) / BS;
+    constexpr int ND = D1 - D0;
+    __shared__ float4 xs[XL];
+    __shared__ float4 lf[XL];
+    const int tid = threadIdx.x;
+    const SimConst c = A.c;
+    for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
+        const int r = A.list[q];
+        const int base = A.robots[r].slot_base;
+        const int pbase = NDIR * base;
+        const size_t rbase = (size_t)A.n_steps * base;
+        const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f), zero = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int i = tid; i < PAD; i += BS) {
+            xs[i] = ghost;
+            xs[PAD + SL + i] = ghost;
+            lf[i] = zero;
+            lf[PAD + SL + i] = zero;
+        }
+        bool pres[NPT];
+        float3 X0[NPT];
+        float pk[NPT][ND], pa[NPT][ND], pb[NPT][ND], pik[NPT][ND], gk[NPT][ND], gs[NPT][ND], gc[NPT][ND];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            const bool live = s < SL;
+            const int sc_ = live ? s : 0;
+            const float4 P0 = A.x0[base + sc_];
+            pres[k] = live && P0.w != 0.f;
+            X0[k] = make_float3(P0.x, P0.y, P0.z);
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                const int pi = pbase + (D0 + j) * SL + sc_;
+                const float kk = live ? A.pl.k[pi] : 0.f;
+                pk[k][j] = kk;
+                pa[k][j] = live ? A.pl.kal[pi] : 0.f;
+                pb[k][j] = (live && PHASE) ? A.pl.kbe[pi] : 0.f;
+                pik[k][j] = kk != 0.f ? 1.0f / kk : 0.f;
+                gk[k][j] = live ? A.gk[pi] : 0.f;
+                gs[k][j] = live ? A.gs[pi] : 0.f;
+                gc[k][j] = live ? A.gc[pi] : 0.f;
+            }
+        }
+        for (int t = A.n_steps - 1; t >= 0; --t) {
+            __syncthreads();  // the previous step's readers are done with the buffers
+            const float2 sct = A.sc[t];
+            float3 Xr[NPT], LF[NPT];
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int s = tid + k * BS;
+                if (s >= SL) continue;
+                float3 X = X0[k];
+                float4 L = zero;
+                if (pres[k]) {
+                    const float4 XR = A.rec_x[rbase + (size_t)t * SL + s];
+                    X = make_float3(XR.x, XR.y, XR.z);
+                    L = A.rec_l[rbase + (size_t)t * SL + s];
+                }
+                Xr[k] = X;
+                LF[k] = make_float3(L.x, L.y, L.z);
+                xs[PAD + s] = make_float4(X.x, X.y, X.z, 0.f);
+                lf[PAD + s] = make_float4(L.x, L.y, L.z, 0.f);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
+                const int s = tid + k * BS;
+                if (s >= SL || !pres[k]) continue;
+#pragma unroll
+                for (int j = 0; j < ND; ++j) {
+                    const int d = D0 + j;
+                    const float3 Y = ld3(xs + s + (PAD + dir_off(d, N)));
+                    const float3 LJ = ld3(lf + s + (PAD + dir_off(d, N)));
+                    const float dx = Y.x - Xr[k].x, dy = Y.y - Xr[k].y, dz = Y.z - Xr[k].z;
+                    const float ux = LJ.x - LF[k].x, uy = LJ.y - LF[k].y, uz = LJ.z - LF[k].z;
+                    const float r2 = len2(dx, dy, dz);
+                    const float ir = __builtin_amdgcn_rsqf(r2);
+                    float kL = fmaf(pa[k][j], sct.x, pk[k][j] * L0d(c, d));
+                    if (PHASE) kL = fmaf(pb[k][j], sct.y, kL);
+                    const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+                    spring_grad_sums(r2, ir, kL, du, pk[k][j], pik[k][j], sct, gk[k][j], gs[k][j], gc[k][j]);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            if (s >= SL) continue;
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                const int pi = pbase + (D0 + j) * SL + s;
+                A.gk[pi] = gk[k][j];
+                A.gs[pi] = gs[k][j];
+                A.gc[pi] = gc[k][j];
             }
         }
         __syncthreads();
@@ -727,6 +863,10 @@ typedef void (*AdjFn)(AArgs);
 struct AdjEntry {
     int n, block;
     AdjFn fn, fn_phase;
+    // split form: fn is the reverse step without gradient sums, and the
+    // gradient pass runs in two launches of gblock threads (directions 0..6, 7..12)
+    int gblock = 0;
+    AdjFn g0 = nullptr, g0_phase = nullptr, g1 = nullptr, g1_phase = nullptr;
 };
 #define SR_AE(NN, BS, X) \
     { NN, BS, k_adjoint<NN + 1, BS, false, X>, k_adjoint<NN + 1, BS, true, X> }
@@ -738,9 +878,17 @@ struct AdjEntry {
     { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, true>, k_adjoint<NN + 1, BS, true, false, 0, true> }
 #define SR_AEF(NN, BS) \
     { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, false, false, true>, k_adjoint<NN + 1, BS, true, false, 0, false, false, true> }
+// split form (sides 10..12): the reverse recursion alone, then the gradient pass
+#define SR_AES(NN, BS, OB, GBS)                                                                                 \
+    {                                                                                                          \
+        NN, BS, k_adjoint<NN + 1, BS, false, false, 0, OB, false, true, true>,                                  \
+            k_adjoint<NN + 1, BS, true, false, 0, OB, false, true, true>, GBS, k_adj_grad<NN + 1, GBS, false, 0, 7>, \
+            k_adj_grad<NN + 1, GBS, true, 0, 7>, k_adj_grad<NN + 1, GBS, false, 7, 13>, k_adj_grad<NN + 1, GBS, true, 7, 13> \
+    }
 const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
                          SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AEL(8, 768, 2),
-                         SR_AEF(9, 1024),       SR_AE(10, 704, false), SR_AE(11, 1024, false), SR_AE1(12, 1024)};
+                         SR_AEF(9, 1024),       SR_AES(10, 704, false, 704), SR_AES(11, 1024, false, 1024),
+                         SR_AES(12, 768, true, 768)};
 // spring dashpots or the damped ground (Table II model): the one-buffer
 // recompute form with the velocity terms
 #define SR_AED(NN, BS) \
@@ -751,10 +899,17 @@ const AdjEntry kAdjD[] = {SR_AED(1, 64),    SR_AED(2, 64),    SR_AED(3, 64),    
 
 }  // namespace
 
+bool adjoint_is_split(int n, bool vel) {
+    if (vel) return false;
+    for (const auto &q : kAdj)
+        if (q.n == n) return q.g0 != nullptr;
+    return false;
+}
+
 hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
                           const float4 *x0, const float4 *rec_x, const float4 *rec_v, const float4 *rec_u,
-                          int n_steps, const float2 *sc, float4 *lx, float4 *lv, float *gk, float *gs, float *gc,
-                          float *gd, SimConst c, hipStream_t st) {
+                          float4 *rec_l, int n_steps, const float2 *sc, float4 *lx, float4 *lv, float *gk, float *gs,
+                          float *gc, float *gd, SimConst c, hipStream_t st) {
     const bool vel = c.dash || c.gdamp;  // forces that depend on the velocities
     if (vel && (!rec_u || !gd)) return hipErrorInvalidValue;
     const AdjEntry *e = nullptr;
@@ -770,6 +925,7 @@ hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int3
     A.rec_x = rec_x;
     A.rec_v = rec_v;
     A.rec_u = rec_u;
+    A.rec_l = rec_l;
     A.n_steps = n_steps;
     A.sc = sc;
     A.lx = lx;
@@ -779,7 +935,34 @@ hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int3
     A.gc = gc;
     A.gd = gd;
     A.c = c;
+    if (e->g0 && !rec_l) return hipErrorInvalidValue;
     hipLaunchKernelGGL(phase ? e->fn_phase : e->fn, dim3(count), dim3(e->block), 0, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_grad(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
+                           const float4 *x0, const float4 *rec_x, float4 *rec_l, int n_steps, const float2 *sc,
+                           float *gk, float *gs, float *gc, SimConst c, hipStream_t st) {
+    const AdjEntry *e = nullptr;
+    for (const auto &q : kAdj)
+        if (q.n == n) e = &q;
+    if (!e || !e->g0 || !rec_l) return hipErrorInvalidValue;
+    AArgs A = {};
+    A.robots = robots;
+    A.list = list;
+    A.count = count;
+    A.pl = pl;
+    A.x0 = x0;
+    A.rec_x = rec_x;
+    A.rec_l = rec_l;
+    A.n_steps = n_steps;
+    A.sc = sc;
+    A.gk = gk;
+    A.gs = gs;
+    A.gc = gc;
+    A.c = c;
+    hipLaunchKernelGGL(phase ? e->g0_phase : e->g0, dim3(count), dim3(e->gblock), 0, st, A);
+    hipLaunchKernelGGL(phase ? e->g1_phase : e->g1, dim3(count), dim3(e->gblock), 0, st, A);
     return hipGetLastError();
 }
 

@@ -123,10 +123,17 @@ hipError_t launch_sincos_at(float2 *sc, int64_t step0, int n, double omega_dt, i
 hipError_t launch_record(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
                          float4 *x, float4 *v, const float2 *sc, int n_steps, uint8_t *diverged, SimConst c,
                          float4 *rec_x, float4 *rec_v, float4 *rec_u, hipStream_t st);
+// reverse step over one recorded segment; for a side whose adjoint is split
+// (adjoint_is_split), rec_l (a buffer like rec_x) takes lambda_F of every step
+// and launch_adj_grad then forms the segment's parameter-gradient sums
+bool adjoint_is_split(int n, bool vel);
+hipError_t launch_adj_grad(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
+                           const float4 *x0, const float4 *rec_x, float4 *rec_l, int n_steps, const float2 *sc,
+                           float *gk, float *gs, float *gc, SimConst c, hipStream_t st);
 hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
                           const float4 *x0, const float4 *rec_x, const float4 *rec_v, const float4 *rec_u,
-                          int n_steps, const float2 *sc, float4 *lx, float4 *lv, float *gk, float *gs, float *gc,
-                          float *gd, SimConst c, hipStream_t st);
+                          float4 *rec_l, int n_steps, const float2 *sc, float4 *lx, float4 *lv, float *gk, float *gs,
+                          float *gc, float *gd, SimConst c, hipStream_t st);
 hipError_t launch_adj_init(const RobotInfo *robots, int total_slots, const int32_t *slot_robot, const float4 *x0,
                            const float *dJ, float4 *lx, float4 *lv, float *gk, float *gs, float *gc, float *gd,
                            hipStream_t st);

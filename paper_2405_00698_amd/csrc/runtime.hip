@@ -123,12 +123,14 @@ struct sr_pop {
     int rec_cap = 0;
     float4 *rec_x[2] = {nullptr, nullptr}, *rec_v[2] = {nullptr, nullptr};
     float4 *rec_u[2] = {nullptr, nullptr};  // v_n per step (dashpots or a damped ground)
+    float4 *rec_l[2] = {nullptr, nullptr};  // lambda_F per step (split adjoint of the largest sides)
     float4 *tmp_x[2] = {nullptr, nullptr}, *tmp_v[2] = {nullptr, nullptr};
     float4 *lx = nullptr, *lv = nullptr;
     float *gk = nullptr, *gs = nullptr, *gc = nullptr, *gd = nullptr, *dJdw = nullptr;
     float2 *sc_seg[2] = {nullptr, nullptr};
-    hipStream_t adj_st = nullptr;
-    hipEvent_t adj_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // start, recorded[2], reversed[2]
+    hipStream_t adj_st = nullptr, adj_gst = nullptr;  // recomputation; gradient passes (split form)
+    // start, recorded[2], reversed[2], gradient sums formed[2]
+    hipEvent_t adj_ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     // captured step graphs: one per (n_steps, mode, current buffer, steps per launch)
     bool use_graphs = true;
     hipStream_t cap = nullptr;
@@ -180,12 +182,14 @@ void pop_free(sr_pop *pop) {
                     pop->d_spring_off, pop->q_cls, pop->q_w, pop->vox_robot, pop->ck_x, pop->ck_v,
                     pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
                     pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs,
-                    pop->gc, pop->gd, pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1]};
+                    pop->gc, pop->gd, pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1],
+                    pop->rec_l[0], pop->rec_l[1]};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto e : pop->adj_ev)
         if (e) (void)hipEventDestroy(e);
     if (pop->adj_st) (void)hipStreamDestroy(pop->adj_st);
+    if (pop->adj_gst) (void)hipStreamDestroy(pop->adj_gst);
 }
 
 int ensure_counts(sr_pop *pop) {
@@ -939,18 +943,22 @@ int ensure_adj_scratch(sr_pop *pop, int K) {
     HIPC(pop, hipStreamSynchronize(pop->st));
     void *old[] = {pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
                    pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs, pop->gc, pop->gd,
-                   pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1]};
+                   pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1], pop->rec_l[0], pop->rec_l[1]};
     for (void *p : old)
         if (p) HIPC(pop, hipFree(p));
     pop->gd = nullptr;
     pop->rec_u[0] = pop->rec_u[1] = nullptr;
+    pop->rec_l[0] = pop->rec_l[1] = nullptr;
     const size_t S = pop->total_slots;
     const bool vel = pop->c.dash || pop->c.gdamp;  // the reverse step needs v_n
+    bool split = false;  // some side's reverse step hands lambda_F to a gradient pass
+    for (const auto &g : pop->groups) split = split || adjoint_is_split(g.n, vel);
     hipError_t e = hipSuccess;
     for (int b = 0; b < 2; ++b) {
         if (e == hipSuccess) e = dalloc(&pop->rec_x[b], S * K);
         if (e == hipSuccess) e = dalloc(&pop->rec_v[b], S * K);
         if (e == hipSuccess && vel) e = dalloc(&pop->rec_u[b], S * K);
+        if (e == hipSuccess && split) e = dalloc(&pop->rec_l[b], S * K);
         if (e == hipSuccess) e = dalloc(&pop->tmp_x[b], S);
         if (e == hipSuccess) e = dalloc(&pop->tmp_v[b], S);
         if (e == hipSuccess) e = dalloc(&pop->sc_seg[b], (size_t)K);
@@ -963,6 +971,7 @@ int ensure_adj_scratch(sr_pop *pop, int K) {
     if (e == hipSuccess && vel) e = dalloc(&pop->gd, S * NDIR);
     if (e == hipSuccess) e = dalloc(&pop->dJdw, (size_t)pop->total_vox);
     if (e == hipSuccess && !pop->adj_st) e = hipStreamCreateWithFlags(&pop->adj_st, hipStreamNonBlocking);
+    if (e == hipSuccess && !pop->adj_gst) e = hipStreamCreateWithFlags(&pop->adj_gst, hipStreamNonBlocking);
     for (auto &ev : pop->adj_ev)
         if (e == hipSuccess && !ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -995,8 +1004,16 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     // Segments are reversed last to first on the population's stream.  The
     // recomputation (checkpoint -> recorded states) of the segment before runs
     // meanwhile on adj_st into the other buffer set, so a population too small
-    // to fill the GPU overlaps the two; events order every buffer reuse.
-    hipEvent_t ev_start = pop->adj_ev[0], *ev_rec = pop->adj_ev + 1, *ev_rev = pop->adj_ev + 3;
+    // to fill the GPU overlaps the two; for the sides whose adjoint is split,
+    // the gradient passes of a segment run on adj_gst while the next segment is
+    // reversed (they read only that segment's buffers and the gradient sums,
+    // which the reversal does not touch).  Events order every buffer reuse.
+    const bool vel = pop->c.dash || pop->c.gdamp;
+    bool split = false;
+    for (const auto &g : pop->groups) split = split || adjoint_is_split(g.n, vel);
+    hipEvent_t ev_start = pop->adj_ev[0], *ev_rec = pop->adj_ev + 1, *ev_rev = pop->adj_ev + 3,
+               *ev_grd = pop->adj_ev + 5;
+    hipEvent_t *ev_free = split ? ev_grd : ev_rev;  // buffer set b's last readers are done
     HIPC(pop, hipEventRecord(ev_start, pop->st));
     HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_start, 0));
     auto recompute = [&](int seg) -> int {
@@ -1004,8 +1021,8 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
         const int64_t s0 = (int64_t)seg * K;
         const int len = (int)((T - s0) < K ? (T - s0) : K);
         const size_t off = (size_t)seg * pop->total_slots;
-        // buffer set b was last read by the reversal of segment seg + 2
-        if (seg + 2 < nseg) HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_rev[b], 0));
+        // buffer set b was last read by the reversal (and gradient passes) of segment seg + 2
+        if (seg + 2 < nseg) HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_free[b], 0));
         HIPC(pop, hipMemcpyAsync(pop->tmp_x[b], pop->ck_x + off, sizeof(float4) * pop->total_slots,
                                  hipMemcpyDeviceToDevice, pop->adj_st));
         HIPC(pop, hipMemcpyAsync(pop->tmp_v[b], pop->ck_v + off, sizeof(float4) * pop->total_slots,
@@ -1027,10 +1044,21 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
         HIPC(pop, hipStreamWaitEvent(pop->st, ev_rec[b], 0));
         for (const auto &gr : pop->groups)
             HIPC(pop, launch_adjoint(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count, pop->pl,
-                                     pop->x0, pop->rec_x[b], pop->rec_v[b], pop->rec_u[b], len, pop->sc_seg[b],
+                                     pop->x0, pop->rec_x[b], pop->rec_v[b], pop->rec_u[b], pop->rec_l[b], len,
+                                     pop->sc_seg[b],
                                      pop->lx, pop->lv, pop->gk, pop->gs, pop->gc, pop->gd, pop->c, pop->st));
         HIPC(pop, hipEventRecord(ev_rev[b], pop->st));
+        if (split) {
+            HIPC(pop, hipStreamWaitEvent(pop->adj_gst, ev_rev[b], 0));
+            for (const auto &gr : pop->groups)
+                if (adjoint_is_split(gr.n, vel))
+                    HIPC(pop, launch_adj_grad(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count,
+                                              pop->pl, pop->x0, pop->rec_x[b], pop->rec_l[b], len, pop->sc_seg[b],
+                                              pop->gk, pop->gs, pop->gc, pop->c, pop->adj_gst));
+            HIPC(pop, hipEventRecord(ev_grd[b], pop->adj_gst));
+        }
     }
+    if (split && nseg > 0) HIPC(pop, hipStreamWaitEvent(pop->st, ev_grd[0], 0));  // segment 0's sums
     HIPC(pop, launch_adj_springs(pop->d_robots, pop->total_slots, pop->slot_robot, pop->sid, pop->d_spring_off, pop->pl,
                                  pop->p.voxel_len, pop->gk, pop->gs, pop->gc, g_k, g_a, g_phi, pop->st));
     if (g_genome)
