@@ -1,10 +1,10 @@
 """Tuner for the persistent step kernel: for every grid side present in a
 population, times each compiled (workgroup size, exchange variant)
-configuration on the live population and keeps the fastest; then, with several
-grid sides, times a few launch schedules of the size groups (which stream each
-side's launch goes to, in which order); then the number of steps per launch
-(the whole call, or the call split into shorter launches) on the whole
-population.  Results are cached in a JSON file keyed by
+configuration on the live population and keeps the fastest; then times, on the
+whole population, a few launch schedules of the size groups (which stream each
+side's launch goes to, in which order; several grid sides only) together with
+the number of steps per launch (the whole call, or the call split into shorter
+launches).  Results are cached in a JSON file keyed by
 (device name, side, population bucket, spring model, the library's
 configuration list for that side)."""
 import hashlib
@@ -105,54 +105,43 @@ def tune(pop, steps=200, cache_path=None, verbose=False):
         pop.set_persist_variant(n, best[0], best[1])
         result[n] = best
         cache[key] = list(best)
-    # launch schedule of the size groups (several sides only): each side's
-    # launch on a stream of its own, largest first (the default), or the
-    # sides dealt largest first round-robin over 2..4 streams, or over three
-    # streams back and forth
+    # launch schedule and steps per launch, together, on the whole population
+    # with the configurations above, timed on calls of at least 2000 steps so
+    # that the launch count is representative.  Schedules (several sides
+    # only): each side's launch on a stream of its own, largest first (the
+    # default), or the sides dealt largest first round-robin over 2..4
+    # streams, or over three streams back and forth.  Steps per launch: the
+    # whole call, or launches of 1000 or 250 steps (sides sharing a stream
+    # then take turns).  The default pair is kept unless another is 3 % faster.
+    desc = sorted(counts, reverse=True)
+    scheds = [list(range(len(desc)))]
     if len(counts) > 1:
-        desc = sorted(counts, reverse=True)
-        ckey = "%s|sched|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
-                                   ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())))
-        cands = [list(range(len(desc)))] + [[i % k for i in range(len(desc))] for k in (2, 3, 4)]
-        cands.append([(i // 3 % 2) * (2 - i % 3) + (1 - i // 3 % 2) * (i % 3) for i in range(len(desc))])
-        if ckey in cache:
-            lanes = list(cache[ckey])
-        else:
-            times = []
-            for lanes in cands:
-                pop.set_schedule(desc, lanes)
-                t = _time(pop, steps)
-                if verbose:
-                    print("schedule %s: %.4f s" % (lanes, t), flush=True)
-                times.append((lanes, t))
-            best = min(times, key=lambda q: q[1])
-            lanes = cands[0] if times[0][1] <= 1.03 * best[1] else best[0]
-            cache[ckey] = lanes
-        pop.set_schedule(desc, lanes)
-    # steps per launch, on the whole population with the configurations and
-    # schedule above: the whole call as one launch per side, or launches of
-    # 1000 or 250 steps (sides that share a stream then take turns), timed on
-    # calls of at least 2000 steps so that the launch count is representative
-    lanes = ",".join(str(q) for q in pop.schedule()[1]) if len(counts) > 1 else "-"
-    skey = "%s|spl|%s|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
-                                ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())), lanes)
+        scheds += [[i % k for i in range(len(desc))] for k in (2, 3, 4)]
+        scheds.append([(i // 3 % 2) * (2 - i % 3) + (1 - i // 3 % 2) * (i % 3) for i in range(len(desc))])
+    skey = "%s|launch|%s|%s" % (dev_name, ",".join("%d:%d" % (n, c) for n, c in sorted(counts.items())),
+                                ",".join("%d:%d:%d" % (n, r[0], r[1]) for n, r in sorted(result.items())))
     if skey in cache:
-        spl = int(cache[skey])
+        lanes, spl = list(cache[skey][0]), int(cache[skey][1])
     else:
         length = max(steps, 2000)
         times = []
-        for c in (0, 1000, 250):
-            if c >= length:
-                continue
-            pop.set_step_config(api._lib.SR_STEP_AUTO, 0, c)
-            t = _time(pop, length)
-            if verbose:
-                print("steps per launch %s: %.4f s" % (c or "all", t), flush=True)
-            times.append((c, t))
-        best = min(times, key=lambda q: q[1])
-        whole = [q for q in times if q[0] == 0][0]
-        spl = 0 if whole[1] <= 1.03 * best[1] else best[0]
-        cache[skey] = spl
+        for lanes in scheds:
+            if len(counts) > 1:
+                pop.set_schedule(desc, lanes)
+            for c in (0, 1000, 250):
+                if c >= length:
+                    continue
+                pop.set_step_config(api._lib.SR_STEP_AUTO, 0, c)
+                t = _time(pop, length)
+                if verbose:
+                    print("schedule %s, steps per launch %s: %.4f s" % (lanes, c or "all", t), flush=True)
+                times.append((lanes, c, t))
+        best = min(times, key=lambda q: q[2])
+        chosen = times[0] if times[0][2] <= 1.03 * best[2] else best
+        lanes, spl = chosen[0], chosen[1]
+        cache[skey] = [lanes, spl]
+    if len(counts) > 1:
+        pop.set_schedule(desc, lanes)
     pop.set_step_config(api._lib.SR_STEP_AUTO, 0, spl)
     pop.steps_per_launch = spl
     pop.reset()
