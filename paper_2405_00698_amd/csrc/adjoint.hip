@@ -525,6 +525,19 @@ __global__ __launch_bounds__(BS) void k_adj_grad(AArgs A) {
                 gc[k][j] = live ? A.gc[pi] : 0.f;
             }
         }
+        // each step's recorded values are loaded one step ahead, so the global
+        // loads are in flight during the previous step's spring work
+        float4 XRn[NPT], LLn[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const int s = tid + k * BS;
+            XRn[k] = zero;
+            LLn[k] = zero;
+            if (pres[k] && A.n_steps > 0) {
+                XRn[k] = A.rec_x[rbase + (size_t)(A.n_steps - 1) * SL + s];
+                LLn[k] = A.rec_l[rbase + (size_t)(A.n_steps - 1) * SL + s];
+            }
+        }
         for (int t = A.n_steps - 1; t >= 0; --t) {
             __syncthreads();  // the previous step's readers are done with the buffers
             const float2 sct = A.sc[t];
@@ -536,9 +549,13 @@ __global__ __launch_bounds__(BS) void k_adj_grad(AArgs A) {
                 float3 X = X0[k];
                 float4 L = zero;
                 if (pres[k]) {
-                    const float4 XR = A.rec_x[rbase + (size_t)t * SL + s];
+                    const float4 XR = XRn[k];
                     X = make_float3(XR.x, XR.y, XR.z);
-                    L = A.rec_l[rbase + (size_t)t * SL + s];
+                    L = LLn[k];
+                    if (t > 0) {
+                        XRn[k] = A.rec_x[rbase + (size_t)(t - 1) * SL + s];
+                        LLn[k] = A.rec_l[rbase + (size_t)(t - 1) * SL + s];
+                    }
                 }
                 Xr[k] = X;
                 LF[k] = make_float3(L.x, L.y, L.z);
@@ -864,7 +881,8 @@ struct AdjEntry {
     int n, block;
     AdjFn fn, fn_phase;
     // split form: fn is the reverse step without gradient sums, and the
-    // gradient pass runs in two launches of gblock threads (directions 0..6, 7..12)
+    // gradient pass runs in one launch of gblock threads (all directions) or
+    // two (directions 0..6, 7..12; g1 set)
     int gblock = 0;
     AdjFn g0 = nullptr, g0_phase = nullptr, g1 = nullptr, g1_phase = nullptr;
 };
@@ -885,9 +903,23 @@ struct AdjEntry {
             k_adjoint<NN + 1, BS, true, false, 0, OB, false, true, true>, GBS, k_adj_grad<NN + 1, GBS, false, 0, 7>, \
             k_adj_grad<NN + 1, GBS, true, 0, 7>, k_adj_grad<NN + 1, GBS, false, 7, 13>, k_adj_grad<NN + 1, GBS, true, 7, 13> \
     }
+// split recompute form with a one-launch gradient pass
+#define SR_AESG(NN, BS, GBS)                                                                                     \
+    {                                                                                                          \
+        NN, BS, k_adjoint<NN + 1, BS, false, false, 0, false, false, true, true>,                               \
+            k_adjoint<NN + 1, BS, true, false, 0, false, false, true, true>, GBS,                               \
+            k_adj_grad<NN + 1, GBS, false, 0, 13>, k_adj_grad<NN + 1, GBS, true, 0, 13>                          \
+    }
+// split exchange form with a one-launch gradient pass
+#define SR_AESL(NN, BS, LG, GBS)                                                                                \
+    {                                                                                                          \
+        NN, BS, k_adjoint<NN + 1, BS, false, true, LG, false, false, false, true>,                              \
+            k_adjoint<NN + 1, BS, true, true, LG, false, false, false, true>, GBS,                              \
+            k_adj_grad<NN + 1, GBS, false, 0, 13>, k_adj_grad<NN + 1, GBS, true, 0, 13>                          \
+    }
 const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
-                         SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AEL(8, 768, 2),
-                         SR_AEF(9, 1024),       SR_AES(10, 704, false, 704), SR_AES(11, 1024, false, 1024),
+                         SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AESL(8, 768, 2, 768),
+                         SR_AESG(9, 1024, 1024), SR_AES(10, 704, false, 704), SR_AES(11, 1024, false, 1024),
                          SR_AES(12, 768, true, 768)};
 // spring dashpots or the damped ground (Table II model): the one-buffer
 // recompute form with the velocity terms
@@ -962,7 +994,7 @@ hipError_t launch_adj_grad(int n, bool phase, const RobotInfo *robots, const int
     A.gc = gc;
     A.c = c;
     hipLaunchKernelGGL(phase ? e->g0_phase : e->g0, dim3(count), dim3(e->gblock), 0, st, A);
-    hipLaunchKernelGGL(phase ? e->g1_phase : e->g1, dim3(count), dim3(e->gblock), 0, st, A);
+    if (e->g1) hipLaunchKernelGGL(phase ? e->g1_phase : e->g1, dim3(count), dim3(e->gblock), 0, st, A);
     return hipGetLastError();
 }
 

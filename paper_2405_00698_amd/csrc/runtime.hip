@@ -34,6 +34,7 @@ static __device__ __align__(256) float2 scratch[SR_NOALLOC_MAX_STEPS];
 
 namespace {
 constexpr int kMaxDevices = 64;
+constexpr int NSET = 3;  // segment buffer sets of the adjoint pipeline
 std::mutex g_scratch_mu;
 float2 *g_scratch[kMaxDevices] = {};
 
@@ -121,16 +122,18 @@ struct sr_pop {
     // (two sets of segment buffers: segment s - 1 is recomputed on adj_st while
     // segment s is reversed on the population's stream)
     int rec_cap = 0;
-    float4 *rec_x[2] = {nullptr, nullptr}, *rec_v[2] = {nullptr, nullptr};
-    float4 *rec_u[2] = {nullptr, nullptr};  // v_n per step (dashpots or a damped ground)
-    float4 *rec_l[2] = {nullptr, nullptr};  // lambda_F per step (split adjoint of the largest sides)
-    float4 *tmp_x[2] = {nullptr, nullptr}, *tmp_v[2] = {nullptr, nullptr};
+    // three sets: while segment s is reversed, segment s - 1 is recomputed and
+    // (split form) the gradient passes of segment s + 1 still read theirs
+    float4 *rec_x[NSET] = {}, *rec_v[NSET] = {};
+    float4 *rec_u[NSET] = {};  // v_n per step (dashpots or a damped ground)
+    float4 *rec_l[NSET] = {};  // lambda_F per step (split adjoint of the largest sides)
+    float4 *tmp_x[NSET] = {}, *tmp_v[NSET] = {};
     float4 *lx = nullptr, *lv = nullptr;
     float *gk = nullptr, *gs = nullptr, *gc = nullptr, *gd = nullptr, *dJdw = nullptr;
-    float2 *sc_seg[2] = {nullptr, nullptr};
+    float2 *sc_seg[NSET] = {};
     hipStream_t adj_st = nullptr, adj_gst = nullptr;  // recomputation; gradient passes (split form)
-    // start, recorded[2], reversed[2], gradient sums formed[2]
-    hipEvent_t adj_ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // start, recorded[NSET], reversed[NSET], gradient sums formed[NSET]
+    hipEvent_t adj_ev[1 + 3 * NSET] = {};
     // captured step graphs: one per (n_steps, mode, current buffer, steps per launch)
     bool use_graphs = true;
     hipStream_t cap = nullptr;
@@ -180,12 +183,15 @@ void pop_free(sr_pop *pop) {
                     pop->slot_node, pop->node_slot, pop->slot_robot, pop->rows, pop->entries,
                     pop->bad_class, pop->diverged, pop->d_step, pop->sc, pop->d_lists, pop->d_mass_off,
                     pop->d_spring_off, pop->q_cls, pop->q_w, pop->vox_robot, pop->ck_x, pop->ck_v,
-                    pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
-                    pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs,
-                    pop->gc, pop->gd, pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1],
-                    pop->rec_l[0], pop->rec_l[1]};
+                    pop->lx, pop->lv, pop->gk, pop->gs, pop->gc, pop->gd, pop->dJdw};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (int b = 0; b < NSET; ++b) {
+        void *seg[] = {pop->rec_x[b], pop->rec_v[b], pop->rec_u[b], pop->rec_l[b], pop->tmp_x[b], pop->tmp_v[b],
+                       pop->sc_seg[b]};
+        for (void *p : seg)
+            if (p) (void)hipFree(p);
+    }
     for (auto e : pop->adj_ev)
         if (e) (void)hipEventDestroy(e);
     if (pop->adj_st) (void)hipStreamDestroy(pop->adj_st);
@@ -941,20 +947,23 @@ namespace {
 int ensure_adj_scratch(sr_pop *pop, int K) {
     if (K <= pop->rec_cap) return SR_OK;
     HIPC(pop, hipStreamSynchronize(pop->st));
-    void *old[] = {pop->rec_x[0], pop->rec_v[0], pop->tmp_x[0], pop->tmp_v[0], pop->rec_x[1], pop->rec_v[1],
-                   pop->tmp_x[1], pop->tmp_v[1], pop->lx, pop->lv, pop->gk, pop->gs, pop->gc, pop->gd,
-                   pop->dJdw, pop->sc_seg[0], pop->sc_seg[1], pop->rec_u[0], pop->rec_u[1], pop->rec_l[0], pop->rec_l[1]};
+    void *old[] = {pop->lx, pop->lv, pop->gk, pop->gs, pop->gc, pop->gd, pop->dJdw};
     for (void *p : old)
         if (p) HIPC(pop, hipFree(p));
+    for (int b = 0; b < NSET; ++b) {
+        void *seg[] = {pop->rec_x[b], pop->rec_v[b], pop->rec_u[b], pop->rec_l[b], pop->tmp_x[b], pop->tmp_v[b],
+                       pop->sc_seg[b]};
+        for (void *p : seg)
+            if (p) HIPC(pop, hipFree(p));
+        pop->rec_u[b] = pop->rec_l[b] = nullptr;
+    }
     pop->gd = nullptr;
-    pop->rec_u[0] = pop->rec_u[1] = nullptr;
-    pop->rec_l[0] = pop->rec_l[1] = nullptr;
     const size_t S = pop->total_slots;
     const bool vel = pop->c.dash || pop->c.gdamp;  // the reverse step needs v_n
     bool split = false;  // some side's reverse step hands lambda_F to a gradient pass
     for (const auto &g : pop->groups) split = split || adjoint_is_split(g.n, vel);
     hipError_t e = hipSuccess;
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < NSET; ++b) {
         if (e == hipSuccess) e = dalloc(&pop->rec_x[b], S * K);
         if (e == hipSuccess) e = dalloc(&pop->rec_v[b], S * K);
         if (e == hipSuccess && vel) e = dalloc(&pop->rec_u[b], S * K);
@@ -1011,18 +1020,18 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     const bool vel = pop->c.dash || pop->c.gdamp;
     bool split = false;
     for (const auto &g : pop->groups) split = split || adjoint_is_split(g.n, vel);
-    hipEvent_t ev_start = pop->adj_ev[0], *ev_rec = pop->adj_ev + 1, *ev_rev = pop->adj_ev + 3,
-               *ev_grd = pop->adj_ev + 5;
+    hipEvent_t ev_start = pop->adj_ev[0], *ev_rec = pop->adj_ev + 1, *ev_rev = pop->adj_ev + 1 + NSET,
+               *ev_grd = pop->adj_ev + 1 + 2 * NSET;
     hipEvent_t *ev_free = split ? ev_grd : ev_rev;  // buffer set b's last readers are done
     HIPC(pop, hipEventRecord(ev_start, pop->st));
     HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_start, 0));
     auto recompute = [&](int seg) -> int {
-        const int b = seg & 1;
+        const int b = seg % NSET;
         const int64_t s0 = (int64_t)seg * K;
         const int len = (int)((T - s0) < K ? (T - s0) : K);
         const size_t off = (size_t)seg * pop->total_slots;
-        // buffer set b was last read by the reversal (and gradient passes) of segment seg + 2
-        if (seg + 2 < nseg) HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_free[b], 0));
+        // buffer set b was last read by the reversal (and gradient passes) of segment seg + NSET
+        if (seg + NSET < nseg) HIPC(pop, hipStreamWaitEvent(pop->adj_st, ev_free[b], 0));
         HIPC(pop, hipMemcpyAsync(pop->tmp_x[b], pop->ck_x + off, sizeof(float4) * pop->total_slots,
                                  hipMemcpyDeviceToDevice, pop->adj_st));
         HIPC(pop, hipMemcpyAsync(pop->tmp_v[b], pop->ck_v + off, sizeof(float4) * pop->total_slots,
@@ -1037,7 +1046,7 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
     };
     if (nseg > 0 && (rc = recompute(nseg - 1))) return rc;
     for (int seg = nseg - 1; seg >= 0; --seg) {
-        const int b = seg & 1;
+        const int b = seg % NSET;
         const int64_t s0 = (int64_t)seg * K;
         const int len = (int)((T - s0) < K ? (T - s0) : K);
         if (seg > 0 && (rc = recompute(seg - 1))) return rc;
