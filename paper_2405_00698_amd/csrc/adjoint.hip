@@ -74,14 +74,21 @@ __device__ __forceinline__ void spring_grad_sums(float r2, float ir, float kL, f
 // FNC: a scheduling barrier after each direction's spring work, so the
 // compiler does not hoist every neighbour read of the slot (which spilled the
 // non-exchange form at 9^3: 1265 VGPRs without, 51 with)
+// XCC (exchange form): the directions are taken in XCC chunks, each with its
+// own forward half, barrier and receiving half, so that only one chunk's rows
+// need LDS (at 9^3-12^3 all 13 directions' rows would not fit beside the
+// state).  Each node then adds its forward springs' terms and subtracts its
+// backward springs' chunk by chunk, so the sums round differently from one
+// chunk (the oracle bounds both).
 // NOG (split form): the reverse step keeps no parameter-gradient sums; it
 // writes each step's lambda_F to rec_l instead, and k_adj_grad forms the sums
 // from the recorded positions and those lambda_F afterwards.  The 13 springs'
 // three sums per slot no longer take registers beside the adjoint recursion.
 template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0, bool ONEBUF = false, bool DASH = false, bool FNC = false,
-          bool NOG = false>
+          bool NOG = false, int XCC = 1>
 __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     static_assert(!NOG || !DASH, "the split form is for the spring model without dashpots");
+    static_assert(XCC == 1 || XCH, "direction chunks are a form of the exchange");
     static_assert(ALAG == 0 || XCH, "pipelined reads are for the exchange form");
     static_assert(!DASH || (!XCH && ONEBUF), "the dashpot adjoint is a one-buffer recompute form");
     using G = Geo<N>;
@@ -89,10 +96,12 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     constexpr int NPT = (SL + BS - 1) / BS;
     constexpr int NBUF = (XCH || ONEBUF) ? 1 : 2;
     constexpr int NQ = XCH ? 1 : NDIR;
+    constexpr int NCH = XCH ? XCC : 1;                 // direction chunks
+    constexpr int NDC = (NDIR + NCH - 1) / NCH;        // directions per chunk
     __shared__ float4 xs[NBUF][XL];
     __shared__ float4 lf[NBUF][XL];
     __shared__ float4 vs[DASH ? NBUF : 1][DASH ? XL : 1];
-    __shared__ float ku[XCH ? 3 * NDIR * CL : 1];
+    __shared__ float ku[XCH ? 3 * NDC * CL : 1];
     const int tid = threadIdx.x;
     const SimConst c = A.c;
     const bool ground = c.ground != 0;
@@ -105,7 +114,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         const size_t rbase = (size_t)A.n_steps * base;
         const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f), zero = make_float4(0.f, 0.f, 0.f, 0.f);
         if (XCH)
-            for (int i = tid; i < 3 * NDIR * CL; i += BS) ku[i] = 0.f;
+            for (int i = tid; i < 3 * NDC * CL; i += BS) ku[i] = 0.f;
         for (int i = tid; i < PAD; i += BS) {
 #pragma unroll
             for (int b = 0; b < NBUF; ++b) {
@@ -191,15 +200,6 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         for (int t = A.n_steps - 1; t >= 0; --t) {
             const int b = NBUF == 1 ? 0 : (t & 1);
             if (NBUF == 1) __syncthreads();  // the previous step's readers are done with the buffers
-#if SR_POISON_LDS
-            // debug build: each thread's own exchange entries hold NaN until it writes them
-            if (XCH)
-                for (int k = 0; k < NPT; ++k) {
-                    const int s = tid + k * BS;
-                    if (s < SL && pres[k])  // absent slots never write theirs (they stay zero)
-                        for (int q = 0; q < 3 * NDIR; ++q) ku[q * CL + PAD + s] = __builtin_nanf("");
-                }
-#endif
             const float2 sct = sc_next;
             if (t > 0) sc_next = A.sc[t - 1];
             float4 XRc[NPT], VPc[NPT], VNc[DASH ? NPT : 1];
@@ -302,28 +302,49 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
             for (int k = 0; k < NPT; ++k) {
                 accs[k] = make_float3(0.f, 0.f, 0.f);
                 if constexpr (DASH) accv[DASH ? k : 0] = make_float3(0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+            const int d0 = ch * NDC, d1 = d0 + NDC < NDIR ? d0 + NDC : NDIR;
+            if (ch > 0) __syncthreads();  // the previous chunk's receivers are done with the rows
+#if SR_POISON_LDS
+            // debug build: each thread's own exchange entries of the chunk hold NaN
+            // until it writes them
+            if (XCH)
+                for (int k = 0; k < NPT; ++k) {
+                    const int s = tid + k * BS;
+                    if (s < SL && pres[k])  // absent slots never write theirs (they stay zero)
+                        for (int q = 0; q < 3; ++q)
+                            for (int j = 0; j < d1 - d0; ++j) ku[(q * NDC + j) * CL + PAD + s] = __builtin_nanf("");
+                }
+#endif
+#pragma unroll
+            for (int k = 0; k < NPT; ++k) {
                 const int s = tid + k * BS;
                 if (s >= SL || !pres[k]) continue;
                 const float4 *xsb = xs[b] + s;
                 const float4 *lfb = lf[b] + s;
                 const float4 *vsb = vs[DASH ? b : 0] + s;
-                float3 acc = make_float3(0.f, 0.f, 0.f), av = make_float3(0.f, 0.f, 0.f);
+                float3 acc = accs[k], av = make_float3(0.f, 0.f, 0.f);
+                if constexpr (DASH) av = accv[DASH ? k : 0];
                 float4 QY[NDIR], QL[NDIR];
                 if constexpr (ALAG > 0) {
 #pragma unroll
-                    for (int d = 0; d < ALAG && d < NDIR; ++d) {
+                    for (int d = 0; d < NDIR; ++d) {
+                        if (d < d0 || d >= d1 || d >= d0 + ALAG) continue;
                         QY[d] = xsb[PAD + dir_off(d, N)];
                         QL[d] = lfb[PAD + dir_off(d, N)];
                     }
                 }
 #pragma unroll
                 for (int d = 0; d < NDIR; ++d) {
+                    if (d < d0 || d >= d1) continue;
                     // forward spring: self is the lower end
                     float3 Y, LJ;
                     if constexpr (ALAG > 0) {
                         constexpr int dummy = 0;
-                        const int e = d + ALAG < NDIR ? d + ALAG : dummy;
-                        if (d + ALAG < NDIR) {
+                        const int e = d + ALAG < d1 ? d + ALAG : dummy;
+                        if (d + ALAG < d1) {
                             QY[e] = xsb[PAD + dir_off(e, N)];
                             QL[e] = lfb[PAD + dir_off(e, N)];
                         }
@@ -367,9 +388,9 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     acc.y += ky;
                     acc.z += kz;
                     if (XCH) {
-                        ku[(0 * NDIR + d) * CL + PAD + s] = kx;
-                        ku[(1 * NDIR + d) * CL + PAD + s] = ky;
-                        ku[(2 * NDIR + d) * CL + PAD + s] = kz;
+                        ku[(0 * NDC + d - d0) * CL + PAD + s] = kx;
+                        ku[(1 * NDC + d - d0) * CL + PAD + s] = ky;
+                        ku[(2 * NDC + d - d0) * CL + PAD + s] = kz;
                     }
                     if constexpr (!NOG)
                         spring_grad_sums(r2, ir, kL, du, pk[k][d], pik[k][d], sct, gk[k][NOG ? 0 : d], gs[k][NOG ? 0 : d],
@@ -427,14 +448,16 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     float3 acc = accs[k];
 #pragma unroll
                     for (int d = 0; d < NDIR; ++d) {
+                        if (d < d0 || d >= d1) continue;
                         const int lo = PAD + s - dir_off(d, N);
-                        acc.x -= ku[(0 * NDIR + d) * CL + lo];
-                        acc.y -= ku[(1 * NDIR + d) * CL + lo];
-                        acc.z -= ku[(2 * NDIR + d) * CL + lo];
+                        acc.x -= ku[(0 * NDC + d - d0) * CL + lo];
+                        acc.y -= ku[(1 * NDC + d - d0) * CL + lo];
+                        acc.z -= ku[(2 * NDC + d - d0) * CL + lo];
                     }
                     accs[k] = acc;
                 }
             }
+            }  // direction chunks
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int s = tid + k * BS;
@@ -917,10 +940,25 @@ struct AdjEntry {
             k_adjoint<NN + 1, BS, true, true, LG, false, false, false, true>, GBS,                              \
             k_adj_grad<NN + 1, GBS, false, 0, 13>, k_adj_grad<NN + 1, GBS, true, 0, 13>                          \
     }
+// split exchange form in XC direction chunks (one chunk's rows in LDS at a
+// time), the gradient pass in one launch (SR_AESC1) or two (SR_AESC)
+#define SR_AESC1(NN, BS, LG, XC, GBS)                                                                           \
+    {                                                                                                          \
+        NN, BS, k_adjoint<NN + 1, BS, false, true, LG, false, false, false, true, XC>,                          \
+            k_adjoint<NN + 1, BS, true, true, LG, false, false, false, true, XC>, GBS,                          \
+            k_adj_grad<NN + 1, GBS, false, 0, 13>, k_adj_grad<NN + 1, GBS, true, 0, 13>                          \
+    }
+#define SR_AESC(NN, BS, LG, XC, GBS)                                                                            \
+    {                                                                                                          \
+        NN, BS, k_adjoint<NN + 1, BS, false, true, LG, false, false, false, true, XC>,                          \
+            k_adjoint<NN + 1, BS, true, true, LG, false, false, false, true, XC>, GBS,                          \
+            k_adj_grad<NN + 1, GBS, false, 0, 7>, k_adj_grad<NN + 1, GBS, true, 0, 7>,                           \
+            k_adj_grad<NN + 1, GBS, false, 7, 13>, k_adj_grad<NN + 1, GBS, true, 7, 13>                          \
+    }
 const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
                          SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AESL(8, 768, 2, 768),
-                         SR_AESG(9, 1024, 1024), SR_AES(10, 704, false, 704), SR_AES(11, 1024, false, 1024),
-                         SR_AES(12, 768, true, 768)};
+                         SR_AESC1(9, 1024, 2, 2, 1024), SR_AESC(10, 768, 2, 3, 704), SR_AESC(11, 768, 2, 4, 1024),
+                         SR_AESC(12, 768, 2, 7, 768)};
 // spring dashpots or the damped ground (Table II model): the one-buffer
 // recompute form with the velocity terms
 #define SR_AED(NN, BS) \

@@ -101,8 +101,8 @@ def _instance_verdict(res, label):
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12])
 def test_spring_gradients_match_oracle_every_side(orc, n):
-    """Every adjoint kernel instance (the exchange forms up to 8^3, the
-    recompute forms of 9^3-11^3, the one-buffer 12^3 form) against the oracle's
+    """Every adjoint kernel instance (the exchange forms, in direction chunks
+    at 9^3-12^3, with the split gradient pass from 8^3 up) against the oracle's
     adjoint at the contact horizon, 200 steps with gravity, ground and
     friction, four robots each.  Odd sides carry per-spring phases (the
     phase-plane kernels)."""

@@ -60,8 +60,10 @@ def test_poisoned_exchange_gives_the_same_bits(n):
     say("side", n, "configurations compared", len(configs))
 
 
-@pytest.mark.parametrize("n", [3, 5, 8])
+@pytest.mark.parametrize("n", [3, 5, 8, 10, 12])
 def test_poisoned_adjoint_exchange_gives_the_same_bits(n):
+    """The exchange rows of the reverse step (one chunk of directions up to 8^3,
+    three at 10^3, seven at 12^3) are all written before they are read."""
     poison = _lib.load(build_lib.LIB_POISON)
     prod = _lib.load()
     sides = [n] * 3
