@@ -1297,11 +1297,19 @@ const PersistEntry kPersist[] = {
             k_persist<NN + 1, BS, 1, false, true, true, true, false, 0, false, LF, LB, SW, SW>, 0        \
     }
 
+// recording forms of the tight-row kernels (balanced slot plan, software-
+// pipelined springs, optionally one position buffer)
+#define SR_RECT(NN, BS, LF, LB, SBX)                                                                             \
+    {                                                                                                          \
+        NN, BS, 1, k_persist<NN + 1, BS, 1, false, false, true, true, false, 0, SBX, LF, LB, true, true, 0, true, true>, \
+            k_persist<NN + 1, BS, 1, false, true, true, true, false, 0, SBX, LF, LB, true, true, 0, true, true>, 0      \
+    }
+
 // recording forms (used to recompute checkpointed segments for the adjoint)
 const PersistEntry kRec[] = {
     SR_REC(1, 64, 1),            SR_REC(2, 64, 1),            SR_REC(3, 64, 1),            SR_RECL(4, 128, 4, 4, false),
     SR_RECL(5, 256, 4, 4, false), SR_RECL(6, 384, 4, 4, false), SR_RECL(7, 512, 4, 4, false), SR_RECL(8, 768, 3, 3, true),
-    SR_RECL(9, 1024, 3, 3, true), SR_RECL(10, 512, 3, 3, true), SR_REC(11, 896, 1),           SR_REC(12, 768, 2),
+    SR_RECL(9, 1024, 3, 3, true), SR_RECT(10, 768, 2, 2, 0),    SR_RECT(11, 1024, 2, 2, 0),  SR_RECT(12, 768, 3, 2, 1),
 };
 
 // recording forms of the spring-dashpot kernels (they carry the phase plane)

@@ -168,6 +168,30 @@ def test_gradients_independent_of_checkpoint_interval():
                 assert np.array_equal(g[key], ref[key]), (K, key)
 
 
+@pytest.mark.parametrize("n", [10, 11, 12])
+def test_recompute_reproduces_the_forward(n):
+    """The recording kernels that recompute each checkpointed segment give the
+    forward kernel's bits: with a checkpoint every step the backward starts
+    each step from the forward's own state, with one segment it recomputes
+    the whole run, and the gradients agree bit for bit."""
+    sides = [n] * 2
+    cls, w = voxel_population(sides, 60 + n)
+    steps = 120
+    dJ = torch.from_numpy(_dJ(len(sides), n)).to(DEV)
+    ref = None
+    for K in (1, 40, steps):
+        say("side", n, "checkpoint interval", K)
+        P = gpu_population(sides, cls, w)
+        P.record(K, steps)
+        P.step(steps)
+        g = {k: v.cpu().numpy() for k, v in P.backward(dJ).items()}
+        if ref is None:
+            ref = g
+        else:
+            for key in ("k", "a", "phi"):
+                assert np.array_equal(g[key], ref[key]), (K, key)
+
+
 def test_genome_gradient_matches_oracle(orc):
     sides = [3] * 6
     B = inputs.gaussian_B()
