@@ -957,8 +957,8 @@ struct AdjEntry {
     }
 const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
                          SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AESL(8, 768, 2, 768),
-                         SR_AESC1(9, 1024, 2, 2, 1024), SR_AESC(10, 768, 2, 3, 704), SR_AESC(11, 768, 1, 4, 1024),
-                         SR_AESC(12, 768, 2, 7, 768)};
+                         SR_AESC1(9, 1024, 2, 2, 1024), SR_AESC(10, 768, 2, 3, 704), SR_AESC(11, 1024, 0, 4, 1024),
+                         SR_AESC(12, 768, 0, 7, 768)};
 // spring dashpots or the damped ground (Table II model): the one-buffer
 // recompute form with the velocity terms
 #define SR_AED(NN, BS) \
