@@ -503,16 +503,14 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
 // to its start as in the fused form, through the same helper: the same bits.
 // One LDS buffer of positions and one of lambda_F, two barriers per step.
 template <int N, int BS, bool PHASE, int D0, int D1>
-__global__ __launch_bounds__(BS) void k_adj_grad(AArgs A) {
+__device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs, float4 *lf) {
     using G = Geo<N>;
-    constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL;
+    constexpr int SL = G::SL, PAD = G::PAD;
     constexpr int NPT = (SL + BS - 1) / BS;
     constexpr int ND = D1 - D0;
-    __shared__ float4 xs[XL];
-    __shared__ float4 lf[XL];
     const int tid = threadIdx.x;
     const SimConst c = A.c;
-    for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
+    {
         const int r = A.list[q];
         const int base = A.robots[r].slot_base;
         const int pbase = NDIR * base;
@@ -620,6 +618,25 @@ __global__ __launch_bounds__(BS) void k_adj_grad(AArgs A) {
             }
         }
         __syncthreads();
+    }
+}
+
+// The gradient pass over directions D0 .. D1 - 1, or (D2 > D1) over D0 .. D1 - 1
+// in the workgroups with blockIdx.y 0 and D1 .. D2 - 1 in those with 1: the two
+// halves of a robot run side by side (they write disjoint sums).
+template <int N, int BS, bool PHASE, int D0, int D1, int D2 = D1>
+__global__ __launch_bounds__(BS) void k_adj_grad(AArgs A) {
+    __shared__ float4 xs[Geo<N>::XL];
+    __shared__ float4 lf[Geo<N>::XL];
+    for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
+        if constexpr (D2 == D1) {
+            adj_grad_robot<N, BS, PHASE, D0, D1>(A, q, xs, lf);
+        } else {
+            if (blockIdx.y == 0)
+                adj_grad_robot<N, BS, PHASE, D0, D1>(A, q, xs, lf);
+            else
+                adj_grad_robot<N, BS, PHASE, D1, D2>(A, q, xs, lf);
+        }
     }
 }
 
@@ -904,10 +921,11 @@ struct AdjEntry {
     int n, block;
     AdjFn fn, fn_phase;
     // split form: fn is the reverse step without gradient sums, and the
-    // gradient pass runs in one launch of gblock threads (all directions) or
-    // two (directions 0..6, 7..12; g1 set)
+    // gradient pass g0 runs gblock threads per workgroup on a grid of robots
+    // x gy (gy 2: directions 0..6 and 7..12 in workgroups side by side)
     int gblock = 0;
-    AdjFn g0 = nullptr, g0_phase = nullptr, g1 = nullptr, g1_phase = nullptr;
+    AdjFn g0 = nullptr, g0_phase = nullptr;
+    int gy = 1;
 };
 #define SR_AE(NN, BS, X) \
     { NN, BS, k_adjoint<NN + 1, BS, false, X>, k_adjoint<NN + 1, BS, true, X> }
@@ -919,20 +937,6 @@ struct AdjEntry {
     { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, true>, k_adjoint<NN + 1, BS, true, false, 0, true> }
 #define SR_AEF(NN, BS) \
     { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, false, false, true>, k_adjoint<NN + 1, BS, true, false, 0, false, false, true> }
-// split form (sides 10..12): the reverse recursion alone, then the gradient pass
-#define SR_AES(NN, BS, OB, GBS)                                                                                 \
-    {                                                                                                          \
-        NN, BS, k_adjoint<NN + 1, BS, false, false, 0, OB, false, true, true>,                                  \
-            k_adjoint<NN + 1, BS, true, false, 0, OB, false, true, true>, GBS, k_adj_grad<NN + 1, GBS, false, 0, 7>, \
-            k_adj_grad<NN + 1, GBS, true, 0, 7>, k_adj_grad<NN + 1, GBS, false, 7, 13>, k_adj_grad<NN + 1, GBS, true, 7, 13> \
-    }
-// split recompute form with a one-launch gradient pass
-#define SR_AESG(NN, BS, GBS)                                                                                     \
-    {                                                                                                          \
-        NN, BS, k_adjoint<NN + 1, BS, false, false, 0, false, false, true, true>,                               \
-            k_adjoint<NN + 1, BS, true, false, 0, false, false, true, true>, GBS,                               \
-            k_adj_grad<NN + 1, GBS, false, 0, 13>, k_adj_grad<NN + 1, GBS, true, 0, 13>                          \
-    }
 // split exchange form with a one-launch gradient pass
 #define SR_AESL(NN, BS, LG, GBS)                                                                                \
     {                                                                                                          \
@@ -941,7 +945,8 @@ struct AdjEntry {
             k_adj_grad<NN + 1, GBS, false, 0, 13>, k_adj_grad<NN + 1, GBS, true, 0, 13>                          \
     }
 // split exchange form in XC direction chunks (one chunk's rows in LDS at a
-// time), the gradient pass in one launch (SR_AESC1) or two (SR_AESC)
+// time), the gradient pass over all directions in one workgroup per robot
+// (SR_AESC1) or in two side by side (SR_AESC)
 #define SR_AESC1(NN, BS, LG, XC, GBS)                                                                           \
     {                                                                                                          \
         NN, BS, k_adjoint<NN + 1, BS, false, true, LG, false, false, false, true, XC>,                          \
@@ -952,8 +957,7 @@ struct AdjEntry {
     {                                                                                                          \
         NN, BS, k_adjoint<NN + 1, BS, false, true, LG, false, false, false, true, XC>,                          \
             k_adjoint<NN + 1, BS, true, true, LG, false, false, false, true, XC>, GBS,                          \
-            k_adj_grad<NN + 1, GBS, false, 0, 7>, k_adj_grad<NN + 1, GBS, true, 0, 7>,                           \
-            k_adj_grad<NN + 1, GBS, false, 7, 13>, k_adj_grad<NN + 1, GBS, true, 7, 13>                          \
+            k_adj_grad<NN + 1, GBS, false, 0, 7, 13>, k_adj_grad<NN + 1, GBS, true, 0, 7, 13>, 2                 \
     }
 const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 64, true),   SR_AEL(4, 128, 2),
                          SR_AEL(5, 256, 2),     SR_AEL(6, 384, 2),     SR_AEL(7, 512, 2),    SR_AESL(8, 768, 2, 768),
@@ -1031,8 +1035,7 @@ hipError_t launch_adj_grad(int n, bool phase, const RobotInfo *robots, const int
     A.gs = gs;
     A.gc = gc;
     A.c = c;
-    hipLaunchKernelGGL(phase ? e->g0_phase : e->g0, dim3(count), dim3(e->gblock), 0, st, A);
-    if (e->g1) hipLaunchKernelGGL(phase ? e->g1_phase : e->g1, dim3(count), dim3(e->gblock), 0, st, A);
+    hipLaunchKernelGGL(phase ? e->g0_phase : e->g0, dim3(count, e->gy), dim3(e->gblock), 0, st, A);
     return hipGetLastError();
 }
 
