@@ -124,6 +124,22 @@ def test_spring_gradients_match_oracle_every_side(orc, n):
     _instance_verdict(res, "side %d" % n)
 
 
+def test_uneven_population_gradients_match_oracle(orc):
+    """One backward over a population of mixed sides: the fused reverse forms
+    (4^3, 5^3, 7^3) and the split ones (8^3, 10^3 and 12^3, with their direction
+    chunks, recording kernels and gradient passes on the other streams) in the
+    same call, each robot against the oracle's adjoint at the contact horizon."""
+    sides = [12, 4, 8, 10, 5, 7, 10, 4]
+    cls, w = voxel_population(sides, 77, p_empty=0.2)
+    steps, K = 200, 50
+    P = gpu_population(sides, cls, w)
+    robots = oracle_robots(orc, sides, cls, w)
+    P.record(K, steps)
+    P.step(steps)
+    res = _compare(P, list(enumerate(robots)), _dJ(len(sides), 9), steps, "uneven")
+    _instance_verdict(res, "uneven")
+
+
 def test_c4_sample_gradients_match_oracle(orc):
     """The differentiation workload (64 robots of 8^3 from random genomes,
     FP32 build, checkpoint every 100 steps): eight sampled robots against the
