@@ -931,12 +931,6 @@ struct AdjEntry {
     { NN, BS, k_adjoint<NN + 1, BS, false, X>, k_adjoint<NN + 1, BS, true, X> }
 #define SR_AEL(NN, BS, LG) \
     { NN, BS, k_adjoint<NN + 1, BS, false, true, LG>, k_adjoint<NN + 1, BS, true, true, LG> }
-// 12^3: the recompute form with one buffer (the exchange rows would need
-// 371 KB of LDS, two buffers 164 KB); its per-slot arrays spill to scratch.
-#define SR_AE1(NN, BS) \
-    { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, true>, k_adjoint<NN + 1, BS, true, false, 0, true> }
-#define SR_AEF(NN, BS) \
-    { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, false, false, true>, k_adjoint<NN + 1, BS, true, false, 0, false, false, true> }
 // split exchange form with a one-launch gradient pass
 #define SR_AESL(NN, BS, LG, GBS)                                                                                \
     {                                                                                                          \
