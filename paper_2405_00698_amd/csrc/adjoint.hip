@@ -90,7 +90,8 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     static_assert(!NOG || !DASH, "the split form is for the spring model without dashpots");
     static_assert(XCC == 1 || XCH, "direction chunks are a form of the exchange");
     static_assert(ALAG == 0 || XCH, "pipelined reads are for the exchange form");
-    static_assert(!DASH || (!XCH && ONEBUF), "the dashpot adjoint is a one-buffer recompute form");
+    static_assert(!DASH || XCH || ONEBUF, "the dashpot adjoint keeps one buffer");
+    static_assert(!DASH || ALAG == 0, "the dashpot exchange reads its neighbours in order");
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD, XL = G::XL, CL = G::CL;
     constexpr int NPT = (SL + BS - 1) / BS;
@@ -98,10 +99,11 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     constexpr int NQ = XCH ? 1 : NDIR;
     constexpr int NCH = XCH ? XCC : 1;                 // direction chunks
     constexpr int NDC = (NDIR + NCH - 1) / NCH;        // directions per chunk
+    constexpr int NR = DASH ? 6 : 3;                   // exchange rows per direction
     __shared__ float4 xs[NBUF][XL];
     __shared__ float4 lf[NBUF][XL];
     __shared__ float4 vs[DASH ? NBUF : 1][DASH ? XL : 1];
-    __shared__ float ku[XCH ? 3 * NDC * CL : 1];
+    __shared__ float ku[XCH ? NR * NDC * CL : 1];
     const int tid = threadIdx.x;
     const SimConst c = A.c;
     const bool ground = c.ground != 0;
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         const size_t rbase = (size_t)A.n_steps * base;
         const float4 ghost = make_float4(1e4f, 1e4f, 1e4f, 0.f), zero = make_float4(0.f, 0.f, 0.f, 0.f);
         if (XCH)
-            for (int i = tid; i < 3 * NDC * CL; i += BS) ku[i] = 0.f;
+            for (int i = tid; i < NR * NDC * CL; i += BS) ku[i] = 0.f;
         for (int i = tid; i < PAD; i += BS) {
 #pragma unroll
             for (int b = 0; b < NBUF; ++b) {
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 for (int k = 0; k < NPT; ++k) {
                     const int s = tid + k * BS;
                     if (s < SL && pres[k])  // absent slots never write theirs (they stay zero)
-                        for (int q = 0; q < 3; ++q)
+                        for (int q = 0; q < NR; ++q)
                             for (int j = 0; j < d1 - d0; ++j) ku[(q * NDC + j) * CL + PAD + s] = __builtin_nanf("");
                 }
 #endif
@@ -382,7 +384,13 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                         av.x = fmaf(cv, dx, av.x);
                         av.y = fmaf(cv, dy, av.y);
                         av.z = fmaf(cv, dz, av.z);
-                        gd[k][DASH ? d : 0] = fmaf(-wv * du, ir2, gd[k][DASH ? d : 0]);
+                        if (XCH) {
+                            // the upper end's velocity-adjoint term, passed like K_s u
+                            ku[(3 * NDC + d - d0) * CL + PAD + s] = cv * dx;
+                            ku[(4 * NDC + d - d0) * CL + PAD + s] = cv * dy;
+                            ku[(5 * NDC + d - d0) * CL + PAD + s] = cv * dz;
+                        }
+                        if constexpr (!NOG) gd[k][DASH ? d : 0] = fmaf(-wv * du, ir2, gd[k][DASH ? d : 0]);
                     }
                     acc.x += kx;
                     acc.y += ky;
@@ -455,6 +463,18 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                         acc.z -= ku[(2 * NDC + d - d0) * CL + lo];
                     }
                     accs[k] = acc;
+                    if constexpr (DASH) {
+                        float3 av = accv[DASH ? k : 0];
+#pragma unroll
+                        for (int d = 0; d < NDIR; ++d) {
+                            if (d < d0 || d >= d1) continue;
+                            const int lo = PAD + s - dir_off(d, N);
+                            av.x -= ku[(3 * NDC + d - d0) * CL + lo];
+                            av.y -= ku[(4 * NDC + d - d0) * CL + lo];
+                            av.z -= ku[(5 * NDC + d - d0) * CL + lo];
+                        }
+                        accv[DASH ? k : 0] = av;
+                    }
                 }
             }
             }  // direction chunks
@@ -961,9 +981,16 @@ const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 
 // recompute form with the velocity terms
 #define SR_AED(NN, BS) \
     { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, true, true>, k_adjoint<NN + 1, BS, true, false, 0, true, true> }
-const AdjEntry kAdjD[] = {SR_AED(1, 64),    SR_AED(2, 64),    SR_AED(3, 64),    SR_AED(4, 128),
-                          SR_AED(5, 256),   SR_AED(6, 384),   SR_AED(7, 512),   SR_AED(8, 768),
-                          SR_AED(9, 1024),  SR_AED(10, 1024), SR_AED(11, 1024), SR_AED(12, 1024)};
+// the exchange form with the velocity terms: six rows per direction (K_s u and
+// the upper end's velocity-adjoint term), XC direction chunks
+#define SR_AEDX(NN, BS, XC)                                                                                    \
+    {                                                                                                          \
+        NN, BS, k_adjoint<NN + 1, BS, false, true, 0, false, true, false, false, XC>,                           \
+            k_adjoint<NN + 1, BS, true, true, 0, false, true, false, false, XC>                                 \
+    }
+const AdjEntry kAdjD[] = {SR_AED(1, 64),        SR_AED(2, 64),        SR_AED(3, 64),        SR_AEDX(4, 128, 1),
+                          SR_AEDX(5, 256, 1),   SR_AEDX(6, 384, 1),   SR_AEDX(7, 512, 2),   SR_AEDX(8, 768, 3),
+                          SR_AEDX(9, 512, 5),   SR_AEDX(10, 768, 7),  SR_AEDX(11, 1024, 13), SR_AED(12, 1024)};
 
 }  // namespace
 

@@ -74,6 +74,21 @@ def test_poisoned_adjoint_exchange_gives_the_same_bits(n):
         assert np.isfinite(q).all() and np.array_equal(p, q)
 
 
+@pytest.mark.parametrize("n", [4, 8, 10])
+def test_poisoned_dashpot_adjoint_exchange_gives_the_same_bits(n):
+    """The dashpot adjoint's six exchange rows per direction (one chunk at 4^3,
+    three at 8^3, seven at 10^3) are all written before they are read."""
+    poison = _lib.load(build_lib.LIB_POISON)
+    prod = _lib.load()
+    sides = [n] * 3
+    cls, w = voxel_population(sides, 150 + n)
+    params = _lib.table2_params()
+    a = _run(prod, sides, cls, w, [None], 120, params=params, record=True)[0]
+    b = _run(poison, sides, cls, w, [None], 120, params=params, record=True)[0]
+    for p, q in zip(a, b):
+        assert np.isfinite(q).all() and np.array_equal(p, q)
+
+
 def test_poisoned_dashpot_kernels_give_the_same_bits():
     poison = _lib.load(build_lib.LIB_POISON)
     prod = _lib.load()

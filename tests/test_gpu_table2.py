@@ -170,10 +170,11 @@ def _adjoint_vs_oracle(orc, sides, seed, steps, over, label):
     return worst
 
 
-@pytest.mark.parametrize("n", [3, 4, 8])
+@pytest.mark.parametrize("n", [3, 4, 7, 8, 9, 10, 11, 12])
 def test_dashpot_adjoint_matches_oracle(orc, n):
     """The adjoint through the spring dashpots and the damped ground (the
-    one-buffer recompute kernels with velocity terms) against the oracle's,
+    exchange kernels with velocity terms, in direction chunks from 7^3 up, and
+    the one-buffer recompute kernels at 1^3-3^3 and 12^3) against the oracle's,
     four robots, 200 steps with contact: the median robot within 1e-3 in
     relative L2 per group, every robot within 5e-2 (single robots may take the
     other stick/slip branch at a near-threshold node)."""
