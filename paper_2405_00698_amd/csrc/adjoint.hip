@@ -87,7 +87,6 @@ __device__ __forceinline__ void spring_grad_sums(float r2, float ir, float kL, f
 template <int N, int BS, bool PHASE, bool XCH, int ALAG = 0, bool ONEBUF = false, bool DASH = false, bool FNC = false,
           bool NOG = false, int XCC = 1>
 __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
-    static_assert(!NOG || !DASH, "the split form is for the spring model without dashpots");
     static_assert(XCC == 1 || XCH, "direction chunks are a form of the exchange");
     static_assert(ALAG == 0 || XCH, "pipelined reads are for the exchange form");
     static_assert(!DASH || XCH || ONEBUF, "the dashpot adjoint keeps one buffer");
@@ -137,7 +136,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
         float qk[NPT][NQ], qa[NPT][NQ], qb[NPT][NQ];
         constexpr int NG = NOG ? 1 : NDIR;
         float gk[NPT][NG], gs[NPT][NG], gc[NPT][NG];
-        float pd[NPT][DASH ? NDIR : 1], qd[NPT][DASH ? NQ : 1], gd[NPT][DASH ? NDIR : 1];
+        float pd[NPT][DASH ? NDIR : 1], qd[NPT][DASH ? NQ : 1], gd[NPT][DASH && !NOG ? NDIR : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int s = tid + k * BS;
@@ -164,7 +163,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                 }
                 if constexpr (DASH) {
                     pd[k][d] = live ? A.pl.kd[pi] : 0.f;
-                    gd[k][d] = live ? A.gd[pi] : 0.f;
+                    if constexpr (!NOG) gd[k][DASH && !NOG ? d : 0] = live ? A.gd[pi] : 0.f;
                 }
             }
             if (!XCH) {
@@ -390,7 +389,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                             ku[(4 * NDC + d - d0) * CL + PAD + s] = cv * dy;
                             ku[(5 * NDC + d - d0) * CL + PAD + s] = cv * dz;
                         }
-                        if constexpr (!NOG) gd[k][DASH ? d : 0] = fmaf(-wv * du, ir2, gd[k][DASH ? d : 0]);
+                        if constexpr (!NOG) gd[k][DASH && !NOG ? d : 0] = fmaf(-wv * du, ir2, gd[k][DASH && !NOG ? d : 0]);
                     }
                     acc.x += kx;
                     acc.y += ky;
@@ -509,7 +508,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     A.gs[pi] = gs[k][NOG ? 0 : d];
                     A.gc[pi] = gc[k][NOG ? 0 : d];
                 }
-                if constexpr (DASH) A.gd[pi] = gd[k][d];
+                if constexpr (DASH && !NOG) A.gd[pi] = gd[k][DASH && !NOG ? d : 0];
             }
         }
         __syncthreads();
@@ -522,8 +521,8 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
 // lambda_F (rec_l; zero on absent slots), step by step from the segment's end
 // to its start as in the fused form, through the same helper: the same bits.
 // One LDS buffer of positions and one of lambda_F, two barriers per step.
-template <int N, int BS, bool PHASE, int D0, int D1>
-__device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs, float4 *lf) {
+template <int N, int BS, bool PHASE, int D0, int D1, bool DASH>
+__device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs, float4 *lf, float4 *vs) {
     using G = Geo<N>;
     constexpr int SL = G::SL, PAD = G::PAD;
     constexpr int NPT = (SL + BS - 1) / BS;
@@ -541,10 +540,15 @@ __device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs
             xs[PAD + SL + i] = ghost;
             lf[i] = zero;
             lf[PAD + SL + i] = zero;
+            if constexpr (DASH) {
+                vs[i] = zero;
+                vs[PAD + SL + i] = zero;
+            }
         }
         bool pres[NPT];
         float3 X0[NPT];
         float pk[NPT][ND], pa[NPT][ND], pb[NPT][ND], pik[NPT][ND], gk[NPT][ND], gs[NPT][ND], gc[NPT][ND];
+        float gd[NPT][DASH ? ND : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int s = tid + k * BS;
@@ -564,44 +568,53 @@ __device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs
                 gk[k][j] = live ? A.gk[pi] : 0.f;
                 gs[k][j] = live ? A.gs[pi] : 0.f;
                 gc[k][j] = live ? A.gc[pi] : 0.f;
+                if constexpr (DASH) gd[k][DASH ? j : 0] = live ? A.gd[pi] : 0.f;
             }
         }
         // each step's recorded values are loaded one step ahead, so the global
         // loads are in flight during the previous step's spring work
-        float4 XRn[NPT], LLn[NPT];
+        float4 XRn[NPT], LLn[NPT], VNn[DASH ? NPT : 1];
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
             const int s = tid + k * BS;
             XRn[k] = zero;
             LLn[k] = zero;
+            if constexpr (DASH) VNn[DASH ? k : 0] = zero;
             if (pres[k] && A.n_steps > 0) {
                 XRn[k] = A.rec_x[rbase + (size_t)(A.n_steps - 1) * SL + s];
                 LLn[k] = A.rec_l[rbase + (size_t)(A.n_steps - 1) * SL + s];
+                if constexpr (DASH) VNn[DASH ? k : 0] = A.rec_u[rbase + (size_t)(A.n_steps - 1) * SL + s];
             }
         }
         for (int t = A.n_steps - 1; t >= 0; --t) {
             __syncthreads();  // the previous step's readers are done with the buffers
             const float2 sct = A.sc[t];
-            float3 Xr[NPT], LF[NPT];
+            float3 Xr[NPT], LF[NPT], Vr[DASH ? NPT : 1];
 #pragma unroll
             for (int k = 0; k < NPT; ++k) {
                 const int s = tid + k * BS;
                 if (s >= SL) continue;
                 float3 X = X0[k];
-                float4 L = zero;
+                float4 L = zero, V = zero;
                 if (pres[k]) {
                     const float4 XR = XRn[k];
                     X = make_float3(XR.x, XR.y, XR.z);
                     L = LLn[k];
+                    if constexpr (DASH) V = VNn[DASH ? k : 0];
                     if (t > 0) {
                         XRn[k] = A.rec_x[rbase + (size_t)(t - 1) * SL + s];
                         LLn[k] = A.rec_l[rbase + (size_t)(t - 1) * SL + s];
+                        if constexpr (DASH) VNn[DASH ? k : 0] = A.rec_u[rbase + (size_t)(t - 1) * SL + s];
                     }
                 }
                 Xr[k] = X;
                 LF[k] = make_float3(L.x, L.y, L.z);
                 xs[PAD + s] = make_float4(X.x, X.y, X.z, 0.f);
                 lf[PAD + s] = make_float4(L.x, L.y, L.z, 0.f);
+                if constexpr (DASH) {
+                    Vr[DASH ? k : 0] = make_float3(V.x, V.y, V.z);
+                    vs[PAD + s] = make_float4(V.x, V.y, V.z, 0.f);
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -621,6 +634,15 @@ __device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs
                     if (PHASE) kL = fmaf(pb[k][j], sct.y, kL);
                     const float du = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
                     spring_grad_sums(r2, ir, kL, du, pk[k][j], pik[k][j], sct, gk[k][j], gs[k][j], gc[k][j]);
+                    if constexpr (DASH) {
+                        // dJ/dc of the dashpot beside the spring, as in the fused reverse step
+                        const float3 VJ = ld3(vs + s + (PAD + dir_off(d, N)));
+                        const float3 VI = Vr[DASH ? k : 0];
+                        const float wx = VJ.x - VI.x, wy = VJ.y - VI.y, wz = VJ.z - VI.z;
+                        const float ir2 = ir * ir;
+                        const float wv = fmaf(dz, wz, fmaf(dy, wy, dx * wx));
+                        gd[k][DASH ? j : 0] = fmaf(-wv * du, ir2, gd[k][DASH ? j : 0]);
+                    }
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -635,6 +657,7 @@ __device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs
                 A.gk[pi] = gk[k][j];
                 A.gs[pi] = gs[k][j];
                 A.gc[pi] = gc[k][j];
+                if constexpr (DASH) A.gd[pi] = gd[k][DASH ? j : 0];
             }
         }
         __syncthreads();
@@ -644,18 +667,20 @@ __device__ __forceinline__ void adj_grad_robot(const AArgs &A, int q, float4 *xs
 // The gradient pass over directions D0 .. D1 - 1, or (D2 > D1) over D0 .. D1 - 1
 // in the workgroups with blockIdx.y 0 and D1 .. D2 - 1 in those with 1: the two
 // halves of a robot run side by side (they write disjoint sums).
-template <int N, int BS, bool PHASE, int D0, int D1, int D2 = D1>
+// DASH: also dJ/dc of the spring dashpots, from the recorded velocities v_n.
+template <int N, int BS, bool PHASE, int D0, int D1, int D2 = D1, bool DASH = false>
 __global__ __launch_bounds__(BS) void k_adj_grad(AArgs A) {
     __shared__ float4 xs[Geo<N>::XL];
     __shared__ float4 lf[Geo<N>::XL];
+    __shared__ float4 vs[DASH ? Geo<N>::XL : 1];
     for (int q = blockIdx.x; q < A.count; q += gridDim.x) {
         if constexpr (D2 == D1) {
-            adj_grad_robot<N, BS, PHASE, D0, D1>(A, q, xs, lf);
+            adj_grad_robot<N, BS, PHASE, D0, D1, DASH>(A, q, xs, lf, vs);
         } else {
             if (blockIdx.y == 0)
-                adj_grad_robot<N, BS, PHASE, D0, D1>(A, q, xs, lf);
+                adj_grad_robot<N, BS, PHASE, D0, D1, DASH>(A, q, xs, lf, vs);
             else
-                adj_grad_robot<N, BS, PHASE, D1, D2>(A, q, xs, lf);
+                adj_grad_robot<N, BS, PHASE, D1, D2, DASH>(A, q, xs, lf, vs);
         }
     }
 }
@@ -988,15 +1013,23 @@ const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 
         NN, BS, k_adjoint<NN + 1, BS, false, true, 0, false, true, false, false, XC>,                           \
             k_adjoint<NN + 1, BS, true, true, 0, false, true, false, false, XC>                                 \
     }
+// split form of the above: the reverse recursion alone, then the gradient
+// pass with the dashpot terms in two direction halves side by side
+#define SR_AEDS(NN, BS, XC, GBS)                                                                               \
+    {                                                                                                          \
+        NN, BS, k_adjoint<NN + 1, BS, false, true, 0, false, true, false, true, XC>,                            \
+            k_adjoint<NN + 1, BS, true, true, 0, false, true, false, true, XC>, GBS,                            \
+            k_adj_grad<NN + 1, GBS, false, 0, 7, 13, true>, k_adj_grad<NN + 1, GBS, true, 0, 7, 13, true>, 2     \
+    }
 const AdjEntry kAdjD[] = {SR_AED(1, 64),        SR_AED(2, 64),        SR_AED(3, 64),        SR_AEDX(4, 128, 1),
-                          SR_AEDX(5, 256, 1),   SR_AEDX(6, 384, 1),   SR_AEDX(7, 512, 2),   SR_AEDX(8, 768, 3),
-                          SR_AEDX(9, 512, 5),   SR_AEDX(10, 768, 7),  SR_AEDX(11, 1024, 13), SR_AED(12, 1024)};
+                          SR_AEDX(5, 256, 1),   SR_AEDX(6, 384, 1),   SR_AEDX(7, 512, 2),   SR_AEDS(8, 768, 3, 768),
+                          SR_AEDS(9, 1024, 5, 1024), SR_AEDS(10, 768, 7, 768), SR_AEDS(11, 1024, 13, 1024),
+                          SR_AED(12, 1024)};
 
 }  // namespace
 
 bool adjoint_is_split(int n, bool vel) {
-    if (vel) return false;
-    for (const auto &q : kAdj)
+    for (const auto &q : (vel ? kAdjD : kAdj))
         if (q.n == n) return q.g0 != nullptr;
     return false;
 }
@@ -1036,10 +1069,12 @@ hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int3
 }
 
 hipError_t launch_adj_grad(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
-                           const float4 *x0, const float4 *rec_x, float4 *rec_l, int n_steps, const float2 *sc,
-                           float *gk, float *gs, float *gc, SimConst c, hipStream_t st) {
+                           const float4 *x0, const float4 *rec_x, const float4 *rec_u, float4 *rec_l, int n_steps,
+                           const float2 *sc, float *gk, float *gs, float *gc, float *gd, SimConst c, hipStream_t st) {
+    const bool vel = c.dash || c.gdamp;
+    if (vel && (!rec_u || !gd)) return hipErrorInvalidValue;
     const AdjEntry *e = nullptr;
-    for (const auto &q : kAdj)
+    for (const auto &q : (vel ? kAdjD : kAdj))
         if (q.n == n) e = &q;
     if (!e || !e->g0 || !rec_l) return hipErrorInvalidValue;
     AArgs A = {};
@@ -1049,12 +1084,14 @@ hipError_t launch_adj_grad(int n, bool phase, const RobotInfo *robots, const int
     A.pl = pl;
     A.x0 = x0;
     A.rec_x = rec_x;
+    A.rec_u = rec_u;
     A.rec_l = rec_l;
     A.n_steps = n_steps;
     A.sc = sc;
     A.gk = gk;
     A.gs = gs;
     A.gc = gc;
+    A.gd = gd;
     A.c = c;
     hipLaunchKernelGGL(phase ? e->g0_phase : e->g0, dim3(count, e->gy), dim3(e->gblock), 0, st, A);
     return hipGetLastError();

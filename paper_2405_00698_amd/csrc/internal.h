@@ -128,8 +128,8 @@ hipError_t launch_record(int n, bool phase, const RobotInfo *robots, const int32
 // and launch_adj_grad then forms the segment's parameter-gradient sums
 bool adjoint_is_split(int n, bool vel);
 hipError_t launch_adj_grad(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
-                           const float4 *x0, const float4 *rec_x, float4 *rec_l, int n_steps, const float2 *sc,
-                           float *gk, float *gs, float *gc, SimConst c, hipStream_t st);
+                           const float4 *x0, const float4 *rec_x, const float4 *rec_u, float4 *rec_l, int n_steps,
+                           const float2 *sc, float *gk, float *gs, float *gc, float *gd, SimConst c, hipStream_t st);
 hipError_t launch_adjoint(int n, bool phase, const RobotInfo *robots, const int32_t *list, int count, Planes pl,
                           const float4 *x0, const float4 *rec_x, const float4 *rec_v, const float4 *rec_u,
                           float4 *rec_l, int n_steps, const float2 *sc, float4 *lx, float4 *lv, float *gk, float *gs,

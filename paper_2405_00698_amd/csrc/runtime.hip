@@ -1062,8 +1062,9 @@ int pop_backward(sr_pop *pop, const float *dJ_dfitness, float *g_k, float *g_a, 
             for (const auto &gr : pop->groups)
                 if (adjoint_is_split(gr.n, vel))
                     HIPC(pop, launch_adj_grad(gr.n, pop->phase, pop->d_robots, pop->d_lists + gr.offset, gr.count,
-                                              pop->pl, pop->x0, pop->rec_x[b], pop->rec_l[b], len, pop->sc_seg[b],
-                                              pop->gk, pop->gs, pop->gc, pop->c, pop->adj_gst));
+                                              pop->pl, pop->x0, pop->rec_x[b], pop->rec_u[b], pop->rec_l[b], len,
+                                              pop->sc_seg[b], pop->gk, pop->gs, pop->gc, pop->gd, pop->c,
+                                              pop->adj_gst));
             HIPC(pop, hipEventRecord(ev_grd[b], pop->adj_gst));
         }
     }

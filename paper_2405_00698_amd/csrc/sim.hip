@@ -1318,10 +1318,27 @@ const PersistEntry kRec[] = {
         NN, BS, VAR + 16, k_persist<NN + 1, BS, VAR, false, true, true, true, true>,                        \
             k_persist<NN + 1, BS, VAR, false, true, true, true, true>, 0                                    \
     }
+// recording forms of the pipelined, tight-row and two-chunk dashpot kernels
+#define SR_RECDF(NN, BS, LF, LB)                                                                             \
+    {                                                                                                       \
+        NN, BS, 1 + 16, k_persist<NN + 1, BS, 1, false, true, true, true, true, 0, false, LF, LB, true, true>, \
+            k_persist<NN + 1, BS, 1, false, true, true, true, true, 0, false, LF, LB, true, true>, 0          \
+    }
+#define SR_RECDT(NN, BS, LF, LB, SBX)                                                                        \
+    {                                                                                                       \
+        NN, BS, 1 + 16,                                                                                     \
+            k_persist<NN + 1, BS, 1, false, true, true, true, true, 0, SBX, LF, LB, true, true, 0, true, true>, \
+            k_persist<NN + 1, BS, 1, false, true, true, true, true, 0, SBX, LF, LB, true, true, 0, true, true>, 0 \
+    }
+#define SR_RECDC(NN, BS)                                                                                     \
+    {                                                                                                       \
+        NN, BS, 2 + 16, k_persist<NN + 1, BS, 2, false, true, true, true, true, 0, true>,                     \
+            k_persist<NN + 1, BS, 2, false, true, true, true, true, 0, true>, 0                               \
+    }
 const PersistEntry kRecD[] = {
-    SR_RECD(1, 64, 1),   SR_RECD(2, 64, 1),   SR_RECD(3, 64, 1),   SR_RECD(4, 128, 1),
-    SR_RECD(5, 256, 1),  SR_RECD(6, 384, 1),  SR_RECD(7, 512, 1),  SR_RECD(8, 768, 1),
-    SR_RECD(9, 768, 1),  SR_RECD(10, 512, 1), SR_RECD(11, 512, 2), SR_RECD(12, 512, 0),
+    SR_RECD(1, 64, 1),         SR_RECD(2, 64, 1),          SR_RECD(3, 64, 1),         SR_RECDF(4, 128, 3, 3),
+    SR_RECDF(5, 256, 3, 3),    SR_RECDF(6, 384, 3, 3),     SR_RECDF(7, 512, 3, 3),    SR_RECDF(8, 768, 3, 3),
+    SR_RECDF(9, 1024, 3, 3),   SR_RECDT(10, 768, 2, 2, 1), SR_RECDT(11, 1024, 1, 1, 1), SR_RECDC(12, 768),
 };
 
 const PersistEntry *find_persist(const PersistCfg &cfg) {
