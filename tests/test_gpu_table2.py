@@ -184,6 +184,16 @@ def test_dashpot_adjoint_matches_oracle(orc, n):
     assert float(np.median(worst)) <= 1e-3
 
 
+def test_dashpot_adjoint_uneven_population_matches_oracle(orc):
+    """One backward over mixed sides of the Table II model: the fused exchange
+    form (5^3), the split forms (8^3, 10^3) and the one-buffer form (12^3) in
+    the same call, against the oracle's adjoint."""
+    worst = _adjoint_vs_oracle(orc, [5, 12, 8, 10, 5, 8], 111, 200, ADJ, "Table II uneven")
+    say("Table II uneven: median %.1e, max %.1e" % (float(np.median(worst)), max(worst)))
+    assert max(worst) <= 5e-2
+    assert float(np.median(worst)) <= 1e-3
+
+
 def test_ground_damper_adjoint_matches_oracle(orc):
     """The damped ground alone (no spring dashpots: the forward runs the
     base-model kernels, the reverse the velocity-aware ones)."""
