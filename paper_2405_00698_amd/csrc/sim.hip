@@ -588,6 +588,12 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                 }
             }
         }
+        // a wave whose 64 slots are all absent lattice points has no spring to
+        // evaluate: its forward coefficients stay the zeros written above, and
+        // absent points are never integrated, so it skips both phases
+        bool wk[NPT];
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) wk[k] = lk[k] && __ballot(pres[k] ? 1 : 0) != 0ull;
         __syncthreads();
 
         float2 sc_next = A.sc[0];
@@ -606,7 +612,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
 #pragma unroll
                 for (int k = 0; k < NPT; ++k) {
                     const int s = sk[k];
-                    if (lk[k]) {
+                    if (wk[k]) {
 #pragma unroll
                         for (int d = 0; d < NDIR; ++d) {
                             const float3 Y = ldx<WIDE>(xc + s + (PAD + dir_off(d, N)));
@@ -662,7 +668,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         // directions keep the zeros of the robot's start (below)
 #pragma unroll
                         for (int k = 0; k < NPT; ++k)
-                            if (lk[k]) {
+                            if (wk[k]) {
                                 const int dw = (CLS && topk[k]) ? (d1 < 4 ? d1 : 4) : d1;
                                 for (int d = d0; d < dw; ++d) coef[(d - d0) * CL + PAD + sk[k]] = __builtin_nanf("");
                             }
@@ -670,7 +676,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int s = sk[k];
-                        if (lk[k]) {
+                        if (wk[k]) {
                             const float4 *xs = xc + s;
                             float *cs = coef + s;
                             int vo = PAD + s;
@@ -716,7 +722,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int s = sk[k];
-                        if (lk[k]) {
+                        if (wk[k]) {
                             const float4 *xs = xc + s;
                             const float *cs = coef + s;
                             auto bwd = [&](int d) {
@@ -753,7 +759,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
                         // directions keep the zeros of the robot's start (below)
 #pragma unroll
                         for (int k = 0; k < NPT; ++k)
-                            if (lk[k]) {
+                            if (wk[k]) {
                                 const int dw = (CLS && topk[k]) ? (d1 < 4 ? d1 : 4) : d1;
                                 for (int d = d0; d < dw; ++d) coef[coef_w<N, TCR>(d, d0) + sk[k]] = __builtin_nanf("");
                             }
@@ -761,7 +767,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int s = sk[k];
-                        if (lk[k]) {
+                        if (wk[k]) {
                             // every neighbour read of this slot is issued before any use;
                             // addresses are one base plus non-negative immediates
                             const float4 *xs = xc + s;
@@ -931,7 +937,7 @@ __global__ __launch_bounds__(BS) void k_persist(PArgs A) {
 #pragma unroll
                     for (int k = 0; k < NPT; ++k) {
                         const int s = sk[k];
-                        if (lk[k]) {
+                        if (wk[k]) {
                             const float4 *xs = xc + s;
                             const float *cs = coef + s;
                             // backward springs of directions d0 .. DE - 1: a run in the bottom
