@@ -92,6 +92,8 @@ def parse():
                     help="run just the adjoint ratio (64 x 8^3) or the uneven 1024-robot generations and print "
                          "their figures (for profiling those workloads)")
     ap.add_argument("--gens", type=int, default=20, help="generations of the uneven workload with --only uneven")
+    ap.add_argument("--adj-side", type=int, default=8, help="grid side of the 64 robots with --only adjoint")
+    ap.add_argument("--adj-table2", action="store_true", help="the Table II model with --only adjoint")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy (HBM counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -261,16 +263,19 @@ def model_rates(api, inputs, torch, R, n, steps, prec, tune_cache):
     return out
 
 
-def adjoint_ratio(api, inputs, torch):
-    """64 robots of 8^3, 2000 steps, checkpoint every 100 steps: pop_backward
-    (segment recompute included) over the forward pop_step(2000), the forward
-    timed both as it runs under recording (checkpoint copies between segment
-    launches) and as the production forward (one captured graph launch)."""
+def adjoint_ratio(api, inputs, torch, n=8, table2=False):
+    """64 robots of 8^3 (or side n; Table II model with table2), 2000 steps,
+    checkpoint every 100 steps: pop_backward (segment recompute included) over
+    the forward pop_step(2000), the forward timed both as it runs under
+    recording (checkpoint copies between segment launches) and as the
+    production forward (one captured graph launch)."""
     from paper_2405_00698_amd import SR_QUERY_FP32
+    from paper_2405_00698_amd._lib import table2_params
     dev = torch.device("cuda:0")
     G = torch.from_numpy(inputs.random_genomes(64)).to(dev)
     B = torch.from_numpy(inputs.gaussian_B()).to(dev)
-    F = api.Population([8] * 64)
+    params = table2_params() if table2 else None
+    F = api.Population([n] * 64, params=params)
     F.build_from_genomes(G, B, SR_QUERY_FP32)
     F.step(2000)
     tg = []
@@ -278,7 +283,7 @@ def adjoint_ratio(api, inputs, torch):
         F.reset()
         tg.append(timed_steps(F, torch, 2000))
     F.close()
-    P = api.Population([8] * 64)
+    P = api.Population([n] * 64, params=params)
     P.build_from_genomes(G, B, SR_QUERY_FP32)
     P.record(100, 2000)
     dJ = torch.ones(64, device=dev)
@@ -296,8 +301,9 @@ def adjoint_ratio(api, inputs, torch):
     P.close()
     f, g, b = float(np.median(tf)), float(np.median(tg)), float(np.median(tb))
     return {"value": b / g, "vs_recording_forward": b / f, "forward_graph_s": g, "forward_recording_s": f,
-            "backward_s": b, "workload": "64 robots of 8^3, 2000 steps, checkpoint every 100, FP32; "
-                                         "value = backward / forward as one graph launch"}
+            "backward_s": b, "workload": "64 robots of %d^3%s, 2000 steps, checkpoint every 100, FP32; "
+                                         "value = backward / forward as one graph launch"
+                                         % (n, " (Table II model)" if table2 else "")}
 
 
 def main():
@@ -315,7 +321,8 @@ def main():
     torch.cuda.set_device(dev)
     tune_cache = "/tmp/softrobot_tune.json"
     if args.only == "adjoint":
-        print(json.dumps({"adjoint_forward_ratio": adjoint_ratio(api, inputs, torch)}), flush=True)
+        print(json.dumps({"adjoint_forward_ratio": adjoint_ratio(api, inputs, torch, args.adj_side,
+                                                                 args.adj_table2)}), flush=True)
         return
     if args.only == "uneven":
         print(json.dumps({"c3_uneven_1024": uneven_generations(api, inputs, torch, 1024, args.gens, 10000,
