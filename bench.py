@@ -17,6 +17,7 @@ Prints one JSON line.  Only one GPU is supported: the population would shard
 across GPUs by robots, which this benchmark does not run.
 """
 import argparse
+import faulthandler
 import json
 import os
 import subprocess
@@ -307,6 +308,8 @@ def adjoint_ratio(api, inputs, torch, n=8, table2=False):
 
 
 def main():
+    # a fatal signal in native code prints the Python stack instead of nothing
+    faulthandler.enable()
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only; the population shards by robots across GPUs, "
