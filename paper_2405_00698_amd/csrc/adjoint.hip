@@ -98,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
     constexpr int NQ = XCH ? 1 : NDIR;
     constexpr int NCH = XCH ? XCC : 1;                 // direction chunks
     constexpr int NDC = (NDIR + NCH - 1) / NCH;        // directions per chunk
-    constexpr int NR = DASH ? 6 : 3;                   // exchange rows per direction
+    constexpr int NR = DASH ? 4 : 3;                   // exchange rows per direction
     __shared__ float4 xs[NBUF][XL];
     __shared__ float4 lf[NBUF][XL];
     __shared__ float4 vs[DASH ? NBUF : 1][DASH ? XL : 1];
@@ -383,12 +383,9 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                         av.x = fmaf(cv, dx, av.x);
                         av.y = fmaf(cv, dy, av.y);
                         av.z = fmaf(cv, dz, av.z);
-                        if (XCH) {
-                            // the upper end's velocity-adjoint term, passed like K_s u
-                            ku[(3 * NDC + d - d0) * CL + PAD + s] = cv * dx;
-                            ku[(4 * NDC + d - d0) * CL + PAD + s] = cv * dy;
-                            ku[(5 * NDC + d - d0) * CL + PAD + s] = cv * dz;
-                        }
+                        // the upper end forms its velocity-adjoint term c du d / r^2
+                        // from this scalar and its own difference vector
+                        if (XCH) ku[(3 * NDC + d - d0) * CL + PAD + s] = cv;
                         if constexpr (!NOG) gd[k][DASH && !NOG ? d : 0] = fmaf(-wv * du, ir2, gd[k][DASH && !NOG ? d : 0]);
                     }
                     acc.x += kx;
@@ -463,14 +460,17 @@ __global__ __launch_bounds__(BS) void k_adjoint(AArgs A) {
                     }
                     accs[k] = acc;
                     if constexpr (DASH) {
+                        // the recompute form's operations at the upper end: d = x_hi - x_lo
                         float3 av = accv[DASH ? k : 0];
 #pragma unroll
                         for (int d = 0; d < NDIR; ++d) {
                             if (d < d0 || d >= d1) continue;
                             const int lo = PAD + s - dir_off(d, N);
-                            av.x -= ku[(3 * NDC + d - d0) * CL + lo];
-                            av.y -= ku[(4 * NDC + d - d0) * CL + lo];
-                            av.z -= ku[(5 * NDC + d - d0) * CL + lo];
+                            const float3 Y = ld3(xs[b] + lo);
+                            const float cv = ku[(3 * NDC + d - d0) * CL + lo];
+                            av.x = fmaf(-cv, Xr[k].x - Y.x, av.x);
+                            av.y = fmaf(-cv, Xr[k].y - Y.y, av.y);
+                            av.z = fmaf(-cv, Xr[k].z - Y.z, av.z);
                         }
                         accv[DASH ? k : 0] = av;
                     }
@@ -1006,8 +1006,8 @@ const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 
 // recompute form with the velocity terms
 #define SR_AED(NN, BS) \
     { NN, BS, k_adjoint<NN + 1, BS, false, false, 0, true, true>, k_adjoint<NN + 1, BS, true, false, 0, true, true> }
-// the exchange form with the velocity terms: six rows per direction (K_s u and
-// the upper end's velocity-adjoint term), XC direction chunks
+// the exchange form with the velocity terms: four rows per direction (K_s u and
+// the scalar of the upper end's velocity-adjoint term), XC direction chunks
 #define SR_AEDX(NN, BS, XC)                                                                                    \
     {                                                                                                          \
         NN, BS, k_adjoint<NN + 1, BS, false, true, 0, false, true, false, false, XC>,                           \
@@ -1022,9 +1022,9 @@ const AdjEntry kAdj[] = {SR_AE(1, 64, true),    SR_AE(2, 64, true),    SR_AE(3, 
             k_adj_grad<NN + 1, GBS, false, 0, 7, 13, true>, k_adj_grad<NN + 1, GBS, true, 0, 7, 13, true>, 2     \
     }
 const AdjEntry kAdjD[] = {SR_AED(1, 64),        SR_AED(2, 64),        SR_AED(3, 64),        SR_AEDX(4, 128, 1),
-                          SR_AEDX(5, 256, 1),   SR_AEDX(6, 384, 1),   SR_AEDX(7, 512, 2),   SR_AEDS(8, 768, 3, 768),
-                          SR_AEDS(9, 1024, 5, 1024), SR_AEDS(10, 768, 7, 768), SR_AEDS(11, 1024, 13, 1024),
-                          SR_AED(12, 1024)};
+                          SR_AEDX(5, 256, 1),   SR_AEDX(6, 384, 1),   SR_AEDX(7, 512, 1),   SR_AEDS(8, 768, 2, 768),
+                          SR_AEDS(9, 1024, 3, 1024), SR_AEDS(10, 768, 5, 768), SR_AEDS(11, 1024, 7, 1024),
+                          SR_AEDS(12, 768, 13, 768)};
 
 }  // namespace
 

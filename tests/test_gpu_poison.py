@@ -76,8 +76,8 @@ def test_poisoned_adjoint_exchange_gives_the_same_bits(n):
 
 @pytest.mark.parametrize("n", [4, 8, 10])
 def test_poisoned_dashpot_adjoint_exchange_gives_the_same_bits(n):
-    """The dashpot adjoint's six exchange rows per direction (one chunk at 4^3,
-    three at 8^3, seven at 10^3) are all written before they are read."""
+    """The dashpot adjoint's four exchange rows per direction (one chunk at 4^3,
+    two at 8^3, five at 10^3) are all written before they are read."""
     poison = _lib.load(build_lib.LIB_POISON)
     prod = _lib.load()
     sides = [n] * 3

@@ -173,8 +173,8 @@ def _adjoint_vs_oracle(orc, sides, seed, steps, over, label):
 @pytest.mark.parametrize("n", [3, 4, 7, 8, 9, 10, 11, 12])
 def test_dashpot_adjoint_matches_oracle(orc, n):
     """The adjoint through the spring dashpots and the damped ground (the
-    exchange kernels with velocity terms, in direction chunks from 7^3 up, and
-    the one-buffer recompute kernels at 1^3-3^3 and 12^3) against the oracle's,
+    exchange kernels with velocity terms, in direction chunks from 8^3 up, and
+    the one-buffer recompute kernels at 1^3-3^3) against the oracle's,
     four robots, 200 steps with contact: the median robot within 1e-3 in
     relative L2 per group, every robot within 5e-2 (single robots may take the
     other stick/slip branch at a near-threshold node)."""
@@ -186,8 +186,8 @@ def test_dashpot_adjoint_matches_oracle(orc, n):
 
 def test_dashpot_adjoint_uneven_population_matches_oracle(orc):
     """One backward over mixed sides of the Table II model: the fused exchange
-    form (5^3), the split forms (8^3, 10^3) and the one-buffer form (12^3) in
-    the same call, against the oracle's adjoint."""
+    form (5^3) and the split forms (8^3, 10^3, 12^3) in the same call, against
+    the oracle's adjoint."""
     worst = _adjoint_vs_oracle(orc, [5, 12, 8, 10, 5, 8], 111, 200, ADJ, "Table II uneven")
     say("Table II uneven: median %.1e, max %.1e" % (float(np.median(worst)), max(worst)))
     assert max(worst) <= 5e-2
